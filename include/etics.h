@@ -1,0 +1,160 @@
+/*
+ * etics.h -- C-ABI of the MI355X expansion force library (libetics.so).
+ *
+ * The library computes the self-consistent-field (SCF) and multipole-expansion
+ * (MEX) gravitational potential and acceleration of N particles, following
+ * Meiron, Li, Holley-Bockelmann & Spurzem, "Expansion Techniques for
+ * Collisionless Stellar Dynamical Simulations" (arXiv:1406.4254):
+ *   - SCF: eq. scf-phi of Section 2.4 with the Hernquist-Ostriker radial basis the
+ *     paper adopts (Section 2.5), basis scale a = 1, G = 1, expansion centre at the
+ *     origin (Section 5.1 leaves centre and length unit to the caller; shift and
+ *     scale the positions before the call);
+ *   - MEX: eqs. mex-phi, mex-qlm, mex-plm of Section 2.4, with particles ordered by
+ *     radius and the inward/outward sums taken exclusively (Section 3.2).
+ *
+ * Memory: every array argument is a DEVICE pointer (for example a torch tensor's
+ * data_ptr()) owned by the caller; the library never frees or keeps them.  Arrays
+ * are structure-of-arrays, FP64, contiguous.  The workspace is caller-allocated
+ * device memory of at least the size returned by the matching *_workspace_size
+ * call, aligned to 256 bytes; its contents need not be initialised and are
+ * undefined after the call.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the legacy default stream).  All
+ * compute calls only enqueue work on that stream and return; none synchronises,
+ * allocates or copies to/from the host, so they may be captured in a hipGraph.
+ *
+ * Errors: 0 on success, otherwise a negative ETICS_E* code; a message for the
+ * last failure of the calling thread is available from etics_last_error().
+ * Arguments are validated before any device work is enqueued, so an invalid call
+ * enqueues nothing.
+ *
+ * Coefficient layout (SCF): for 0 <= n <= nmax, 0 <= m <= l <= lmax,
+ *   idx(n,l,m) = n (lmax+1)(lmax+2)/2 + l(l+1)/2 + m,   K = (nmax+1)(lmax+1)(lmax+2)/2.
+ * A[idx] and B[idx] are the cosine and sine coefficients of
+ *   Phi(r,theta,phi) = sum_{n,l,m>=0} PhiT_nl(r) Ybar_lm(theta) (A cos m phi + B sin m phi),
+ * with PhiT_nl the Hernquist-Ostriker radial functions, Ybar_lm the orthonormal
+ * Legendre amplitude (Condon-Shortley phase) and the (2 - delta_m0) factor of the
+ * real form already applied; B[idx(n,l,0)] = 0.  The paper's complex coefficient
+ * (Section 2.4, m >= 0) is (A - iB)/(2 - delta_m0).  The SCF coefficients include
+ * every particle; MEX excludes the particle itself.
+ */
+#ifndef ETICS_H
+#define ETICS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* precision modes: basis evaluation / force synthesis precision and the
+   cross-particle reduction precision */
+#define ETICS_FP64 0          /* everything in FP64 */
+#define ETICS_MIXED_FP64ACC 1 /* FP32 basis and synthesis, FP64 coefficient reduction */
+#define ETICS_MIXED_COMP32 2  /* FP32 basis and synthesis, compensated (double-float) FP32 reduction */
+
+/* outputs of the force calls (bit mask) */
+#define ETICS_POT 1
+#define ETICS_ACC 2
+#define ETICS_POT_ACC 3
+
+/* return codes */
+#define ETICS_OK 0
+#define ETICS_EINVAL (-1)        /* bad size, cutoff, mode or a required NULL pointer */
+#define ETICS_EWORKSPACE (-2)    /* workspace missing or smaller than required */
+#define ETICS_EHIP (-3)          /* a HIP runtime or launch error */
+#define ETICS_EUNSUPPORTED (-4)  /* valid request this build does not implement */
+
+/* expansion cutoffs supported by this build */
+#define ETICS_NMAX_CAP 20
+#define ETICS_LMAX_CAP 14
+
+/* Number of (A,B) coefficient pairs K = (nmax+1)(lmax+1)(lmax+2)/2 (Section 2.4,
+   after eq. scf-phi; 308 at (10,6)).  Returns -1 for cutoffs outside the caps. */
+int etics_coeff_count(int nmax, int lmax);
+
+/* Workspace bytes needed by etics_scf_coeffs and etics_scf_force for n particles;
+   0 if the arguments are invalid.  Host-only, enqueues nothing. */
+size_t etics_scf_workspace_size(int64_t n, int nmax, int lmax, int precision);
+
+/* SCF expansion coefficients (Section 2.4, eq. scf-phi; Section 3.3 computes them
+   as the first part of a force calculation).
+   x,y,z,m: [n] particle positions and masses.  A,B: [K] outputs (overwritten).
+   n = 0 is valid and yields zero coefficients.  The cross-particle sums are taken
+   in a fixed order, so repeated calls with the same inputs, sizes and precision
+   give bitwise-identical results. */
+int etics_scf_coeffs(const double* x, const double* y, const double* z, const double* m,
+                     int64_t n, int nmax, int lmax, int precision,
+                     double* A, double* B, void* workspace, size_t ws_bytes, void* stream);
+
+/* SCF potential and acceleration a = -grad Phi at the points x,y,z [n] from
+   coefficients A,B [K] (Section 3.3, the second part of a force calculation).
+   outputs: ETICS_POT, ETICS_ACC or both.  pot may be NULL unless POT is requested,
+   ax/ay/az may be NULL unless ACC is requested.  A point exactly at the origin gets
+   no l = 0 force (its direction is undefined there). */
+int etics_scf_force(const double* x, const double* y, const double* z, int64_t n,
+                    int nmax, int lmax, const double* A, const double* B, int precision,
+                    int outputs, double* pot, double* ax, double* ay, double* az,
+                    void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes needed by etics_mex_force; 0 if the arguments are invalid. */
+size_t etics_mex_workspace_size(int64_t n, int lmax, int precision);
+
+/* MEX potential and acceleration of every particle from all the others (Section
+   2.4, eqs. mex-phi/qlm/plm; Section 3.2).  Particles are ordered by the FP64 key
+   (x*x + y*y) + z*z (each operation rounded, no fused multiply-add), ties broken by
+   index; the inward sums q run over particles before i, the outward sums p over
+   particles after i.  ETICS_MIXED_* evaluate the angular functions in FP32 and keep
+   radial powers, the ordered sums and the synthesis accumulation in FP64.  A
+   particle exactly at the origin has no inward part and adds nothing to the outward
+   sums. */
+int etics_mex_force(const double* x, const double* y, const double* z, const double* m,
+                    int64_t n, int lmax, int precision, int outputs,
+                    double* pot, double* ax, double* ay, double* az,
+                    void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for the batched SCF calls and the batched leapfrog over nsys
+   systems with ntotal particles in all; 0 if the arguments are invalid. */
+size_t etics_batched_workspace_size(int64_t ntotal, int nsys, int nmax, int lmax, int precision);
+
+/* Batched SCF coefficients of nsys independent systems stored back to back:
+   system s is particles offsets[s] .. offsets[s+1]-1 (offsets: DEVICE int64
+   [nsys+1], non-decreasing, offsets[0] = 0, offsets[nsys] = ntotal).  A,B: [nsys*K],
+   system s at s*K.  Each system's coefficients equal what etics_scf_coeffs returns
+   for that system alone, up to the summation order. */
+int etics_scf_coeffs_batched(const double* x, const double* y, const double* z, const double* m,
+                             const int64_t* offsets, int nsys, int64_t ntotal, int nmax, int lmax,
+                             int precision, double* A, double* B,
+                             void* workspace, size_t ws_bytes, void* stream);
+
+/* Batched SCF potential/acceleration: particle i of system s feels system s's
+   coefficients A,B [nsys*K]. */
+int etics_scf_force_batched(const double* x, const double* y, const double* z,
+                            const int64_t* offsets, int nsys, int64_t ntotal, int nmax, int lmax,
+                            const double* A, const double* B, int precision, int outputs,
+                            double* pot, double* ax, double* ay, double* az,
+                            void* workspace, size_t ws_bytes, void* stream);
+
+/* nsteps kick-drift-kick leapfrog steps of dt for nsys independent systems, each
+   feeling only its own SCF field (the paper integrates with a leapfrog, Section
+   3.4):  v += dt/2 a(x);  x += dt v;  v += dt/2 a(x).  x..vz are updated in place.
+   The first call for a given (pointers, sizes, precision, dt) captures one step
+   into a hipGraph and later calls replay it; the graph is rebuilt when any of them
+   changes.  Runs on `stream`; returns after enqueueing. */
+int etics_leapfrog_scf_batched(double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                               const double* m, const int64_t* offsets, int nsys, int64_t ntotal,
+                               int nmax, int lmax, int precision, double dt, int nsteps,
+                               void* workspace, size_t ws_bytes, void* stream);
+
+/* Message describing the last non-zero return on the calling thread ("" if none). */
+const char* etics_last_error(void);
+
+/* Library version string. */
+const char* etics_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ETICS_H */

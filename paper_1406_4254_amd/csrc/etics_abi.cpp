@@ -1,0 +1,158 @@
+// etics_abi.cpp -- the C-ABI entry points of libetics.so: argument validation,
+// workspace sizing and dispatch to the HIP kernels.  No entry point allocates,
+// synchronises or copies to/from the host.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "etics_internal.hpp"
+
+namespace etics {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int hip_fail(hipError_t e, const char* where) {
+  if (e == hipSuccess) return ETICS_OK;
+  set_error(std::string(where) + ": " + hipGetErrorString(e));
+  return ETICS_EHIP;
+}
+
+static int einval(const char* what) {
+  set_error(std::string("invalid argument: ") + what);
+  return ETICS_EINVAL;
+}
+
+static bool valid_prec(int p) {
+  return p == ETICS_FP64 || p == ETICS_MIXED_FP64ACC || p == ETICS_MIXED_COMP32;
+}
+
+static bool valid_cut(int nmax, int lmax) {
+  return nmax >= 0 && nmax <= ETICS_NMAX_CAP && lmax >= 0 && lmax <= ETICS_LMAX_CAP;
+}
+
+static const size_t kAlign = 256;
+
+size_t scf_ws_bytes(int64_t n, int nmax, int lmax, int prec) {
+  CoeffPlan p;
+  if (!make_coeff_plan(n, nmax, lmax, prec, &p)) return 0;
+  size_t a = align_up(coeff_partials_bytes(p), kAlign);
+  size_t b = align_up(force_prep_bytes(nmax, lmax, prec), kAlign);
+  return a > b ? a : b;
+}
+
+}  // namespace etics
+
+using namespace etics;
+
+extern "C" {
+
+int etics_coeff_count(int nmax, int lmax) {
+  if (!valid_cut(nmax, lmax)) return -1;
+  return coeff_count(nmax, lmax);
+}
+
+const char* etics_last_error(void) { return g_last_error.c_str(); }
+
+const char* etics_version(void) { return "etics-mi355x 0.1 (gfx950)"; }
+
+size_t etics_scf_workspace_size(int64_t n, int nmax, int lmax, int precision) {
+  if (n < 0 || !valid_cut(nmax, lmax) || !valid_prec(precision)) return 0;
+  return scf_ws_bytes(n, nmax, lmax, precision);
+}
+
+int etics_scf_coeffs(const double* x, const double* y, const double* z, const double* m,
+                     int64_t n, int nmax, int lmax, int precision, double* A, double* B,
+                     void* workspace, size_t ws_bytes, void* stream) {
+  if (n < 0) return einval("n < 0");
+  if (!valid_cut(nmax, lmax)) return einval("nmax/lmax outside [0, cap]");
+  if (!valid_prec(precision)) return einval("precision");
+  if (!A || !B) return einval("A/B is NULL");
+  if (n > 0 && (!x || !y || !z || !m)) return einval("x/y/z/m is NULL");
+  const size_t need = scf_ws_bytes(n, nmax, lmax, precision);
+  if (need == 0) {
+    set_error("no tile plan for these cutoffs");
+    return ETICS_EUNSUPPORTED;
+  }
+  if (!workspace || ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return ETICS_EWORKSPACE;
+  }
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return einval("workspace not 256-byte aligned");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int K = coeff_count(nmax, lmax);
+  if (n == 0) {
+    int rc = launch_fill_zero(A, K, st);
+    return rc ? rc : launch_fill_zero(B, K, st);
+  }
+  CoeffPlan p;
+  make_coeff_plan(n, nmax, lmax, precision, &p);
+  return launch_scf_coeffs(p, x, y, z, m, n, A, B, workspace, st);
+}
+
+int etics_scf_force(const double* x, const double* y, const double* z, int64_t n, int nmax,
+                    int lmax, const double* A, const double* B, int precision, int outputs,
+                    double* pot, double* ax, double* ay, double* az, void* workspace,
+                    size_t ws_bytes, void* stream) {
+  if (n < 0) return einval("n < 0");
+  if (!valid_cut(nmax, lmax)) return einval("nmax/lmax outside [0, cap]");
+  if (!valid_prec(precision)) return einval("precision");
+  if (outputs < 1 || outputs > 3) return einval("outputs");
+  if (!A || !B) return einval("A/B is NULL");
+  if (n > 0 && (!x || !y || !z)) return einval("x/y/z is NULL");
+  if (n > 0 && (outputs & ETICS_POT) && !pot) return einval("pot is NULL");
+  if (n > 0 && (outputs & ETICS_ACC) && (!ax || !ay || !az)) return einval("ax/ay/az is NULL");
+  const size_t need = scf_ws_bytes(n, nmax, lmax, precision);
+  if (need == 0) {
+    set_error("no tile plan for these cutoffs");
+    return ETICS_EUNSUPPORTED;
+  }
+  if (!workspace || ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return ETICS_EWORKSPACE;
+  }
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return einval("workspace not 256-byte aligned");
+  if (n == 0) return ETICS_OK;
+  return launch_scf_force(x, y, z, n, nmax, lmax, A, B, precision, outputs, pot, ax, ay, az,
+                          workspace, reinterpret_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------- not yet built
+size_t etics_mex_workspace_size(int64_t n, int lmax, int precision) {
+  (void)n; (void)lmax; (void)precision;
+  return 0;
+}
+
+int etics_mex_force(const double*, const double*, const double*, const double*, int64_t, int,
+                    int, int, double*, double*, double*, double*, void*, size_t, void*) {
+  set_error("etics_mex_force: not implemented in this build");
+  return ETICS_EUNSUPPORTED;
+}
+
+size_t etics_batched_workspace_size(int64_t, int, int, int, int) { return 0; }
+
+int etics_scf_coeffs_batched(const double*, const double*, const double*, const double*,
+                             const int64_t*, int, int64_t, int, int, int, double*, double*, void*,
+                             size_t, void*) {
+  set_error("etics_scf_coeffs_batched: not implemented in this build");
+  return ETICS_EUNSUPPORTED;
+}
+
+int etics_scf_force_batched(const double*, const double*, const double*, const int64_t*, int,
+                            int64_t, int, int, const double*, const double*, int, int, double*,
+                            double*, double*, double*, void*, size_t, void*) {
+  set_error("etics_scf_force_batched: not implemented in this build");
+  return ETICS_EUNSUPPORTED;
+}
+
+int etics_leapfrog_scf_batched(double*, double*, double*, double*, double*, double*,
+                               const double*, const int64_t*, int, int64_t, int, int, int, double,
+                               int, void*, size_t, void*) {
+  set_error("etics_leapfrog_scf_batched: not implemented in this build");
+  return ETICS_EUNSUPPORTED;
+}
+
+}  // extern "C"
