@@ -3,6 +3,7 @@
 // synchronises or copies to/from the host.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -120,18 +121,37 @@ int etics_scf_force(const double* x, const double* y, const double* z, int64_t n
                           workspace, reinterpret_cast<hipStream_t>(stream));
 }
 
-// ---------------------------------------------------------------- not yet built
 size_t etics_mex_workspace_size(int64_t n, int lmax, int precision) {
-  (void)n; (void)lmax; (void)precision;
-  return 0;
+  if (n < 0 || n > INT32_MAX || lmax < 0 || lmax > ETICS_LMAX_CAP || !valid_prec(precision)) return 0;
+  return mex_ws_bytes(n, lmax);
 }
 
-int etics_mex_force(const double*, const double*, const double*, const double*, int64_t, int,
-                    int, int, double*, double*, double*, double*, void*, size_t, void*) {
-  set_error("etics_mex_force: not implemented in this build");
-  return ETICS_EUNSUPPORTED;
+int etics_mex_force(const double* x, const double* y, const double* z, const double* m, int64_t n,
+                    int lmax, int precision, int outputs, double* pot, double* ax, double* ay,
+                    double* az, void* workspace, size_t ws_bytes, void* stream) {
+  if (n < 0) return einval("n < 0");
+  if (n > INT32_MAX) {
+    set_error("etics_mex_force: n must be below 2^31 (32-bit sort indices)");
+    return ETICS_EUNSUPPORTED;
+  }
+  if (lmax < 0 || lmax > ETICS_LMAX_CAP) return einval("lmax outside [0, cap]");
+  if (!valid_prec(precision)) return einval("precision");
+  if (outputs < 1 || outputs > 3) return einval("outputs");
+  if (n > 0 && (!x || !y || !z || !m)) return einval("x/y/z/m is NULL");
+  if (n > 0 && (outputs & ETICS_POT) && !pot) return einval("pot is NULL");
+  if (n > 0 && (outputs & ETICS_ACC) && (!ax || !ay || !az)) return einval("ax/ay/az is NULL");
+  const size_t need = mex_ws_bytes(n, lmax);
+  if (!workspace || ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return ETICS_EWORKSPACE;
+  }
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return einval("workspace not 256-byte aligned");
+  if (n == 0) return ETICS_OK;
+  return launch_mex_force(x, y, z, m, n, lmax, precision, outputs, pot, ax, ay, az, workspace,
+                          reinterpret_cast<hipStream_t>(stream));
 }
 
+// ---------------------------------------------------------------- not yet built
 size_t etics_batched_workspace_size(int64_t, int, int, int, int) { return 0; }
 
 int etics_scf_coeffs_batched(const double*, const double*, const double*, const double*,

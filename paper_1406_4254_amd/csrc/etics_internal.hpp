@@ -7,7 +7,7 @@
 #include <cstdint>
 #include <string>
 
-#include "../../include/etics.h"
+#include "etics.h"
 #include "etics_tables.hpp"
 
 namespace etics {
@@ -27,16 +27,15 @@ constexpr int kMaxStreams = 32;
 
 struct CoeffPlan {
   int nmax, lmax, prec;   // prec: ETICS_* precision mode
+  int lb;                 // compile-time lmax bucket of the kernel (lmax <= lb)
   int nb, bs;             // register block: nb radial orders x bs angular slots
-  int tp;                 // particles per tile
-  int nrow;               // floats per (particle, l) radial row (multiple of 4, >= nchunks*nb)
-  int nchunks;            // radial chunks of nb
+  int nchunks;            // radial chunks of nb orders
   int spg, spz;           // LDS strides (elements) per particle: radial rows, angular slots
+  int tp;                 // particles per tile
   int nblocks, streams;   // register blocks per stream, streams per workgroup
   int flush_tiles;        // FP32 run length (tiles) before folding into the wide accumulator
   int grid;               // workgroups
   size_t lds_bytes;
-  int zoff[LCAP + 2];     // first angular slot of each l inside a particle's slot row
 };
 
 bool make_coeff_plan(int64_t n, int nmax, int lmax, int prec, CoeffPlan* p);
@@ -51,5 +50,10 @@ int launch_scf_coeffs(const CoeffPlan& p, const double* x, const double* y, cons
 int launch_scf_force(const double* x, const double* y, const double* z, int64_t n, int nmax,
                      int lmax, const double* A, const double* B, int prec, int outputs,
                      double* pot, double* ax, double* ay, double* az, void* ws, hipStream_t st);
+
+size_t mex_ws_bytes(int64_t n, int lmax);
+int launch_mex_force(const double* x, const double* y, const double* z, const double* m, int64_t n,
+                     int lmax, int prec, int outputs, double* pot, double* ax, double* ay,
+                     double* az, void* ws, hipStream_t st);
 
 }  // namespace etics

@@ -1,0 +1,111 @@
+"""GPU parity of the MEX path (through the C-ABI) against the FP64 CPU oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_1406_4254_amd import accuracy as acc  # noqa: E402
+from paper_1406_4254_amd import workloads as W  # noqa: E402
+
+FP64, MIXED, COMP32 = 0, 1, 2
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1406_4254_amd import etics
+    etics.lib()
+    return etics
+
+
+def gpu_mex(E, x, y, z, m, lmax, prec, outputs=3):
+    import torch
+    d = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in (x, y, z, m)]
+    r = E.etics_mex_force(*d, lmax, prec, outputs)
+    return [None if t is None else t.cpu().numpy() for t in r]
+
+
+def check(tag, got, ref, fmed, fp99, fmax=None):
+    pot, ax, ay, az = got
+    rp, rx, ry, rz = ref
+    ef = acc.summarize(acc.force_rel_err(ax, ay, az, rx, ry, rz))
+    ep = acc.summarize(acc.pot_rel_err(pot, rp))
+    print(f"{tag}: force {ef} pot {ep}", flush=True)
+    assert ef["median"] <= fmed and ef["p99"] <= fp99
+    assert ep["median"] <= fmed and ep["p99"] <= fp99
+    if fmax is not None:
+        assert ef["max"] <= fmax and ep["max"] <= fmax
+
+
+@pytest.mark.parametrize("lmax", [0, 1, 3, 6, 10, 14])
+def test_mex_fp64_matches_oracle(E, orc, lmax):
+    p = W.make_config(4, 3001)
+    got = gpu_mex(E, p.x, p.y, p.z, p.m, lmax, FP64)
+    ref = orc.mex_force(p.x, p.y, p.z, p.m, lmax)
+    check(f"mex fp64 l{lmax}", got, ref, 1e-12, 1e-11, 1e-9)
+
+
+@pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 4097, 9000])
+def test_mex_ragged_sizes(E, orc, n):
+    p = W.make_config(4, n)
+    got = gpu_mex(E, p.x, p.y, p.z, p.m, 4, FP64)
+    ref = orc.mex_force(p.x, p.y, p.z, p.m, 4)
+    if n == 1:  # a lone particle feels nothing
+        assert np.all(got[0] == 0.0) and np.all(got[1] == 0.0)
+        return
+    check(f"mex ragged n{n}", got, ref, 1e-12, 1e-11, 1e-9)
+
+
+@pytest.mark.parametrize("prec", [MIXED, COMP32])
+def test_mex_mixed_accuracy(E, orc, prec):
+    p = W.make_config(4, 40_000)
+    got = gpu_mex(E, p.x, p.y, p.z, p.m, 10, prec)
+    ref = orc.mex_force(p.x, p.y, p.z, p.m, 10)
+    check(f"mex prec{prec}", got, ref, 1e-5, 1e-4)
+
+
+def test_mex_ties_keep_index_order(E, orc):
+    """Mirror copies (x -> -x) have bitwise-equal radius keys; equal keys are ordered by
+    index, as in the oracle."""
+    p = W.make_config(4, 1500)
+    x = np.concatenate([p.x, -p.x])
+    y = np.concatenate([p.y, p.y])
+    z = np.concatenate([p.z, p.z])
+    m = np.concatenate([p.m, p.m]) * 0.5
+    got = gpu_mex(E, x, y, z, m, 6, FP64)
+    ref = orc.mex_force(x, y, z, m, 6)
+    check("mex ties", got, ref, 1e-12, 1e-11, 1e-9)
+
+
+def test_mex_origin_particle(E, orc):
+    p = W.make_config(4, 700)
+    x, y, z = p.x.copy(), p.y.copy(), p.z.copy()
+    x[5] = y[5] = z[5] = 0.0
+    x[9] = y[9] = 0.0
+    got = gpu_mex(E, x, y, z, p.m, 5, FP64)
+    ref = orc.mex_force(x, y, z, p.m, 5)
+    assert all(np.all(np.isfinite(g)) for g in got)
+    check("mex origin", got, ref, 1e-12, 1e-11, 1e-9)
+
+
+def test_mex_output_modes(E):
+    p = W.make_config(4, 3000)
+    both = gpu_mex(E, p.x, p.y, p.z, p.m, 6, MIXED, 3)
+    pot = gpu_mex(E, p.x, p.y, p.z, p.m, 6, MIXED, 1)
+    accel = gpu_mex(E, p.x, p.y, p.z, p.m, 6, MIXED, 2)
+    assert np.array_equal(pot[0], both[0])
+    for k in (1, 2, 3):
+        assert np.array_equal(accel[k], both[k])
+
+
+def test_mex_cfg4_full_size(E, orc):
+    """N = 10^6 Plummer + Hernquist mixture at lmax = 10: every particle."""
+    p = W.make_config(4)
+    ref = orc.mex_force(p.x, p.y, p.z, p.m, 10)
+    for prec in (MIXED, FP64):
+        got = gpu_mex(E, p.x, p.y, p.z, p.m, 10, prec)
+        if prec == FP64:
+            check("mex cfg4 fp64", got, ref, 1e-12, 1e-10)
+        else:
+            check("mex cfg4 mixed", got, ref, 1e-5, 1e-4)
