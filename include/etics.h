@@ -21,7 +21,10 @@
  *
  * Streams: `stream` is a hipStream_t (NULL = the legacy default stream).  All
  * compute calls only enqueue work on that stream and return; none synchronises,
- * allocates or copies to/from the host, so they may be captured in a hipGraph.
+ * allocates device memory or copies to/from the host, so they may be captured in a
+ * hipGraph.  The one exception is etics_leapfrog_scf_batched, which itself captures
+ * a step into a hipGraph: on first use it creates a library stream and instantiates
+ * the graph (it must not be called inside another capture).
  *
  * Errors: 0 on success, otherwise a negative ETICS_E* code; a message for the
  * last failure of the calling thread is available from etics_last_error().
@@ -136,15 +139,23 @@ int etics_scf_force_batched(const double* x, const double* y, const double* z,
                             double* pot, double* ax, double* ay, double* az,
                             void* workspace, size_t ws_bytes, void* stream);
 
+/* leapfrog flags */
+#define ETICS_LEAPFROG_EAGER 1 /* launch each step's kernels directly instead of replaying the graph */
+
 /* nsteps kick-drift-kick leapfrog steps of dt for nsys independent systems, each
    feeling only its own SCF field (the paper integrates with a leapfrog, Section
-   3.4):  v += dt/2 a(x);  x += dt v;  v += dt/2 a(x).  x..vz are updated in place.
-   The first call for a given (pointers, sizes, precision, dt) captures one step
-   into a hipGraph and later calls replay it; the graph is rebuilt when any of them
-   changes.  Runs on `stream`; returns after enqueueing. */
+   3.4):  v += dt/2 a(x);  x += dt v;  a = a(x);  v += dt/2 a.  x..vz are updated in
+   place; m and offsets are as for the batched calls.  Every call first computes
+   a(x) at the current positions (one extra force calculation), then runs the steps.
+   Unless ETICS_LEAPFROG_EAGER is set, one step is captured into a hipGraph on a
+   library stream (the first time for a given set of pointers, sizes, precision, dt
+   and workspace; a different set replaces the cached graph) and replayed nsteps
+   times on `stream`; graph and eager runs launch the same kernels with the same
+   arguments, so they give bitwise-equal results.  The cache is shared by all threads
+   of the process (calls are serialised by a lock).  nsteps = 0 does nothing. */
 int etics_leapfrog_scf_batched(double* x, double* y, double* z, double* vx, double* vy, double* vz,
                                const double* m, const int64_t* offsets, int nsys, int64_t ntotal,
-                               int nmax, int lmax, int precision, double dt, int nsteps,
+                               int nmax, int lmax, int precision, double dt, int nsteps, int flags,
                                void* workspace, size_t ws_bytes, void* stream);
 
 /* Message describing the last non-zero return on the calling thread ("" if none). */

@@ -151,28 +151,101 @@ int etics_mex_force(const double* x, const double* y, const double* z, const dou
                           reinterpret_cast<hipStream_t>(stream));
 }
 
-// ---------------------------------------------------------------- not yet built
-size_t etics_batched_workspace_size(int64_t, int, int, int, int) { return 0; }
-
-int etics_scf_coeffs_batched(const double*, const double*, const double*, const double*,
-                             const int64_t*, int, int64_t, int, int, int, double*, double*, void*,
-                             size_t, void*) {
-  set_error("etics_scf_coeffs_batched: not implemented in this build");
-  return ETICS_EUNSUPPORTED;
+// ---------------------------------------------------------------- batched + leapfrog
+static int check_batched(int64_t ntotal, int nsys, int nmax, int lmax, int prec, const void* offsets) {
+  if (ntotal < 0) return einval("ntotal < 0");
+  if (nsys < 1) return einval("nsys < 1");
+  if (!valid_cut(nmax, lmax)) return einval("nmax/lmax outside [0, cap]");
+  if (!valid_prec(prec)) return einval("precision");
+  if (!offsets) return einval("offsets is NULL");
+  if (ntotal / kUnitParticles + nsys > INT32_MAX / 2) {
+    set_error("too many particles or systems for 32-bit unit indices");
+    return ETICS_EUNSUPPORTED;
+  }
+  return ETICS_OK;
 }
 
-int etics_scf_force_batched(const double*, const double*, const double*, const int64_t*, int,
-                            int64_t, int, int, const double*, const double*, int, int, double*,
-                            double*, double*, double*, void*, size_t, void*) {
-  set_error("etics_scf_force_batched: not implemented in this build");
-  return ETICS_EUNSUPPORTED;
+size_t etics_batched_workspace_size(int64_t ntotal, int nsys, int nmax, int lmax, int precision) {
+  if (ntotal < 0 || nsys < 1 || !valid_cut(nmax, lmax) || !valid_prec(precision)) return 0;
+  if (ntotal / kUnitParticles + nsys > INT32_MAX / 2) return 0;
+  return batched_layout(ntotal, nsys, nmax, lmax, precision).total;
 }
 
-int etics_leapfrog_scf_batched(double*, double*, double*, double*, double*, double*,
-                               const double*, const int64_t*, int, int64_t, int, int, int, double,
-                               int, void*, size_t, void*) {
-  set_error("etics_leapfrog_scf_batched: not implemented in this build");
-  return ETICS_EUNSUPPORTED;
+int etics_scf_coeffs_batched(const double* x, const double* y, const double* z, const double* m,
+                             const int64_t* offsets, int nsys, int64_t ntotal, int nmax, int lmax,
+                             int precision, double* A, double* B, void* workspace, size_t ws_bytes,
+                             void* stream) {
+  int rc = check_batched(ntotal, nsys, nmax, lmax, precision, offsets);
+  if (rc) return rc;
+  if (!A || !B) return einval("A/B is NULL");
+  if (ntotal > 0 && (!x || !y || !z || !m)) return einval("x/y/z/m is NULL");
+  const BatchedLayout L = batched_layout(ntotal, nsys, nmax, lmax, precision);
+  if (!workspace || ws_bytes < L.total) {
+    set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
+    return ETICS_EWORKSPACE;
+  }
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return einval("workspace not 256-byte aligned");
+  CoeffPlan plan;
+  if (!make_coeff_plan(kUnitParticles, nmax, lmax, precision, &plan)) {
+    set_error("no tile plan for these cutoffs");
+    return ETICS_EUNSUPPORTED;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* base = reinterpret_cast<char*>(workspace);
+  int* ustart = reinterpret_cast<int*>(base + L.off_ustart);
+  int* usys = reinterpret_cast<int*>(base + L.off_usys);
+  rc = launch_units(offsets, nsys, ntotal, ustart, usys, st);
+  if (rc) return rc;
+  return launch_scf_coeffs_batched(plan, x, y, z, m, offsets, ustart, usys, nsys, ntotal, A, B,
+                                   base + L.off_partials, st);
+}
+
+int etics_scf_force_batched(const double* x, const double* y, const double* z,
+                            const int64_t* offsets, int nsys, int64_t ntotal, int nmax, int lmax,
+                            const double* A, const double* B, int precision, int outputs,
+                            double* pot, double* ax, double* ay, double* az, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  int rc = check_batched(ntotal, nsys, nmax, lmax, precision, offsets);
+  if (rc) return rc;
+  if (outputs < 1 || outputs > 3) return einval("outputs");
+  if (!A || !B) return einval("A/B is NULL");
+  if (ntotal > 0 && (!x || !y || !z)) return einval("x/y/z is NULL");
+  if (ntotal > 0 && (outputs & ETICS_POT) && !pot) return einval("pot is NULL");
+  if (ntotal > 0 && (outputs & ETICS_ACC) && (!ax || !ay || !az)) return einval("ax/ay/az is NULL");
+  const BatchedLayout L = batched_layout(ntotal, nsys, nmax, lmax, precision);
+  if (!workspace || ws_bytes < L.total) {
+    set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
+    return ETICS_EWORKSPACE;
+  }
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return einval("workspace not 256-byte aligned");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* base = reinterpret_cast<char*>(workspace);
+  int* ustart = reinterpret_cast<int*>(base + L.off_ustart);
+  int* usys = reinterpret_cast<int*>(base + L.off_usys);
+  rc = launch_units(offsets, nsys, ntotal, ustart, usys, st);
+  if (rc) return rc;
+  return launch_scf_force_batched(x, y, z, offsets, ustart, usys, nsys, ntotal, nmax, lmax, A, B,
+                                  precision, outputs, pot, ax, ay, az, base + L.off_prep, st);
+}
+
+int etics_leapfrog_scf_batched(double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                               const double* m, const int64_t* offsets, int nsys, int64_t ntotal,
+                               int nmax, int lmax, int precision, double dt, int nsteps, int flags,
+                               void* workspace, size_t ws_bytes, void* stream) {
+  int rc = check_batched(ntotal, nsys, nmax, lmax, precision, offsets);
+  if (rc) return rc;
+  if (nsteps < 0) return einval("nsteps < 0");
+  if (!(dt == dt)) return einval("dt is NaN");
+  if (ntotal > 0 && (!x || !y || !z || !vx || !vy || !vz || !m)) return einval("state pointer is NULL");
+  const BatchedLayout L = batched_layout(ntotal, nsys, nmax, lmax, precision);
+  if (!workspace || ws_bytes < L.total) {
+    set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
+    return ETICS_EWORKSPACE;
+  }
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return einval("workspace not 256-byte aligned");
+  if (nsteps == 0 || ntotal == 0) return ETICS_OK;
+  return run_leapfrog(x, y, z, vx, vy, vz, m, offsets, nsys, ntotal, nmax, lmax, precision, dt,
+                      nsteps, flags, workspace, ws_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -161,50 +161,242 @@ __device__ __forceinline__ void decode_block(int b, int lmax, int nchunks, int& 
   }
 }
 
+// One workgroup's share of the coefficient sums: the LDS tile, the register block
+// of each lane, and the three steps (basis -> LDS, accumulate, merge and write).
+template <typename T, int LB, int NB, int BS, int MODE>
+struct CoeffWG {
+  static constexpr int NRP = nrp_for_nb(NB);
+  static constexpr int SPG = g_stride(LB, NRP);
+  static constexpr int SPZ = z_stride(LB, BS);
+  using PT = typename PartialT<(sizeof(T) == 4 && MODE == 1) ? 1 : 0>::type;
+
+  T* G;  // [tp][SPG]  radial values, rows of NRP per l
+  T* Z;  // [tp][SPZ]  angular values x mass x radial prefactor
+  int tid, lane, wave, maxm_w, lmax, nmax, tp, streams, nblocks, nchunks;
+  int my_stream, my_block, bl, n0, s0;
+  bool active;
+  T acc[NB][BS];
+  Wide<T, MODE> wide[NB][BS];
+
+  __device__ __forceinline__ void init(unsigned char* lds, int tp_, int lmax_, int nmax_,
+                                       int nblocks_, int streams_, int nchunks_) {
+    constexpr JobPlan<LB, NRP> kJP = make_job_plan<LB, NRP>();
+    G = reinterpret_cast<T*>(lds);
+    Z = G + tp_ * SPG;
+    tid = threadIdx.x;
+    lane = tid & 63;
+    wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    tp = tp_;
+    lmax = lmax_;
+    nmax = nmax_;
+    nblocks = nblocks_;
+    streams = streams_;
+    nchunks = nchunks_;
+    // largest angular column owned by this wavefront (the diagonal walk stops there)
+    maxm_w = -1;
+    static_for<4>([&](auto wc) {
+      if (wave == decltype(wc)::value) maxm_w = kJP.maxm[decltype(wc)::value];
+    });
+    my_stream = tid / nblocks;
+    my_block = tid - my_stream * nblocks;
+    active = my_stream < streams;
+    decode_block<NB, BS>(my_block, lmax, nchunks, bl, n0, s0);
+    clear_acc();
+    clear_wide();
+  }
+
+  __device__ __forceinline__ void clear_acc() {
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < BS; ++j) acc[i][j] = T(0);
+  }
+  __device__ __forceinline__ void clear_wide() {
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < BS; ++j) wide[i][j] = Wide<T, MODE>{};
+  }
+  // angular padding slots are never written by phase 1; keep them finite
+  __device__ __forceinline__ void zero_slots() {
+    for (int i = tid; i < tp * SPZ; i += kCoeffThreads) Z[i] = T(0);
+  }
+  // fold the FP32 run into the wide accumulators
+  __device__ __forceinline__ void fold() {
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < BS; ++j) {
+        wide[i][j].add(acc[i][j]);
+        acc[i][j] = T(0);
+      }
+  }
+
+  // phase 1: basis of the particle of this lane (zero mass for an empty lane)
+  __device__ __forceinline__ void phase1(double xd, double yd, double zd, double md) {
+    constexpr JobPlan<LB, NRP> kJP = make_job_plan<LB, NRP>();
+    if (lane >= tp) return;
+    const Sph<T> s = sph<T>(xd, yd, zd);
+    const T tu = s.t * s.u, ctu = s.ct * tu, tu2 = tu * tu, stu = s.st * tu;
+    T* Gp = G + lane * SPG;
+    T* Zp = Z + lane * SPZ;
+    // angular jobs: column m of mass u (tu)^l Ybar_lm (cos, sin)(m phi), l = m..lmax.
+    // The diagonal value mass u (tu)^m Ybar_mm and (cos, sin)(m phi) are walked up to
+    // the largest column this wavefront owns.
+    T Pd = T(md) * s.u * T(kTab.c1[0][0]);
+    T cmc = T(1), smc = T(0);
+    static_for<LB + 1>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      if constexpr (m > 0) {
+        if (m <= maxm_w) {
+          Pd = (T(kTab.c1[m][m]) * stu) * Pd;
+          const T c2 = cmc * s.cp - smc * s.sp;
+          smc = smc * s.cp + cmc * s.sp;
+          cmc = c2;
+        }
+      }
+      if (wave == kJP.ownerZ[m] && m <= lmax) {
+        constexpr int sc = m == 0 ? 0 : 2 * m - 1;
+        T P2 = T(0), P1 = Pd;
+        Zp[zoff(m, BS) + sc] = P1 * cmc;
+        if constexpr (m > 0) Zp[zoff(m, BS) + sc + 1] = P1 * smc;
+        static_for<LB - m>([&](auto kc) {
+          constexpr int l = m + 1 + decltype(kc)::value;
+          if (l <= lmax) {
+            const T P = (T(kTab.c1[l][m]) * ctu) * P1 - (T(kTab.c2[l][m]) * tu2) * P2;
+            P2 = P1;
+            P1 = P;
+            Zp[zoff(l, BS) + sc] = P * cmc;
+            if constexpr (m > 0) Zp[zoff(l, BS) + sc + 1] = P * smc;
+          }
+        });
+      }
+    });
+    // radial jobs: monic Gegenbauer Chat_n^(2l+3/2)(xi), n = 0..NRP-1.  Entries past
+    // nmax only feed coefficients that are never written out; they stay finite.
+    static_for<LB + 1>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      if (wave == kJP.ownerG[l] && l <= lmax) {
+        T p2 = T(1), p1 = T(0);
+        static_for<NRP / 4>([&](auto qc) {
+          constexpr int nb4 = 4 * decltype(qc)::value;
+          T v[4];
+          static_for<4>([&](auto jc) {
+            constexpr int nn = nb4 + decltype(jc)::value;
+            const T c = s.xi * p1 - T(kTab.q[l][nn]) * p2;
+            p2 = p1;
+            p1 = c;
+            v[decltype(jc)::value] = c;
+          });
+          T* row = Gp + l * NRP + nb4;
+          if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4*>(row) = make_float4(v[0], v[1], v[2], v[3]);
+          } else {
+            *reinterpret_cast<double2*>(row) = make_double2(v[0], v[1]);
+            *reinterpret_cast<double2*>(row + 2) = make_double2(v[2], v[3]);
+          }
+        });
+      }
+    });
+  }
+
+  // phase 2: outer-product accumulation over the tile
+  __device__ __forceinline__ void phase2() {
+    if (!active) return;
+    const T* gbase = G + bl * NRP + n0;
+    const T* zbase = Z + zoff_rt<BS>(bl) + s0;
+    constexpr int NG = (NB + 3) / 4 * 4;
+    T gv[2][NG], zv[2][BS];
+    auto fetch = [&](int p, int buf) {
+      const T* g = gbase + p * SPG;
+      const T* zz = zbase + p * SPZ;
+      if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int q = 0; q < NG / 4; ++q) {
+          const float4 f = reinterpret_cast<const float4*>(g)[q];
+          gv[buf][4 * q] = f.x;
+          gv[buf][4 * q + 1] = f.y;
+          gv[buf][4 * q + 2] = f.z;
+          gv[buf][4 * q + 3] = f.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < (NB + 1) / 2; ++q) {
+          const double2 f = reinterpret_cast<const double2*>(g)[q];
+          gv[buf][2 * q] = f.x;
+          gv[buf][2 * q + 1] = f.y;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < BS; ++j) zv[buf][j] = zz[j];
+    };
+    auto madd = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < BS; ++j) acc[i][j] = fma_(gv[buf][i], zv[buf][j], acc[i][j]);
+    };
+    // two particles per trip, each one's LDS reads issued before the other's FMAs
+    int p = my_stream;
+    if (p < tp) fetch(p, 0);
+    for (; p + streams < tp; p += 2 * streams) {
+      fetch(p + streams, 1);
+      madd(0);
+      if (p + 2 * streams < tp) fetch(p + 2 * streams, 0);
+      madd(1);
+    }
+    if (p < tp) madd(0);
+  }
+
+  // merge the streams in a fixed order through LDS (overwrites the tile) and write the
+  // partial sums in coefficient layout: part[0..K) cos, part[K..2K) sin
+  __device__ __forceinline__ void merge_write(unsigned char* lds, PT* part, int K) {
+    PT* out = reinterpret_cast<PT*>(lds);
+    for (int s = 0; s < streams; ++s) {
+      if (active && my_stream == s) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int j = 0; j < BS; ++j) {
+            const int e = (my_block * NB + i) * BS + j;
+            const PT v = wide_value(wide[i][j]);
+            out[e] = (s == 0) ? v : merge(out[e], v);
+          }
+      }
+      __syncthreads();
+    }
+    const int L2 = (lmax + 1) * (lmax + 2) / 2;
+    const int nent = nblocks * NB * BS;
+    for (int e = tid; e < nent; e += kCoeffThreads) {
+      const int j = e % BS;
+      const int i = (e / BS) % NB;
+      int l, nb0, sb0;
+      decode_block<NB, BS>(e / (NB * BS), lmax, nchunks, l, nb0, sb0);
+      const int nn = nb0 + i;
+      const int slot = sb0 + j;
+      if (nn > nmax || slot > 2 * l) continue;
+      const int m = (slot + 1) / 2;
+      const bool is_sin = slot > 0 && (slot & 1) == 0;
+      const int k = nn * L2 + l * (l + 1) / 2 + m;
+      part[(is_sin ? K : 0) + k] = out[e];
+    }
+  }
+};
+
 template <typename T, int LB, int NB, int BS, int MODE>
 __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coeff_kernel(
     const CoeffArgs a) {
-  constexpr int NRP = nrp_for_nb(NB);
-  constexpr int SPG = g_stride(LB, NRP);
-  constexpr int SPZ = z_stride(LB, BS);
-  constexpr JobPlan<LB, NRP> kJP = make_job_plan<LB, NRP>();
-
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* G = reinterpret_cast<T*>(lds_raw);  // [tp][SPG]  radial values, rows of NRP per l
-  T* Z = G + a.tp * SPG;                 // [tp][SPZ]  angular values x mass x radial prefactor
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lmax = a.lmax, nmax = a.nmax;
-
-  // largest angular column owned by this wavefront (the diagonal walk stops there)
-  int maxm_w = -1;
-  static_for<4>([&](auto wc) {
-    if (wave == decltype(wc)::value) maxm_w = kJP.maxm[decltype(wc)::value];
-  });
-
-  // register block owned by this thread
-  const int my_stream = tid / a.nblocks;
-  const int my_block = tid - my_stream * a.nblocks;
-  const bool active = my_stream < a.streams;
-  int bl, n0, s0;
-  decode_block<NB, BS>(my_block, lmax, a.nchunks, bl, n0, s0);
-
-  T acc[NB][BS];
-  Wide<T, MODE> wide[NB][BS];
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < BS; ++j) acc[i][j] = T(0);
-
-  // angular padding slots are never written by phase 1; keep them finite
-  for (int i = tid; i < a.tp * SPZ; i += kCoeffThreads) Z[i] = T(0);
+  CoeffWG<T, LB, NB, BS, MODE> w;
+  w.init(lds_raw, a.tp, a.lmax, a.nmax, a.nblocks, a.streams, a.nchunks);
+  w.zero_slots();
   __syncthreads();
 
   // particle data of the first tile (later tiles are prefetched during phase 2)
   double xd = 0.0, yd = 0.0, zd = 0.0, md = 0.0;
   auto load_particle = [&](int tile) {
-    const int64_t pi = int64_t(tile) * a.tp + lane;
-    const bool valid = tile < a.ntiles && lane < a.tp && pi < a.n;
+    const int64_t pi = int64_t(tile) * a.tp + w.lane;
+    const bool valid = tile < a.ntiles && w.lane < a.tp && pi < a.n;
     xd = valid ? a.x[pi] : 0.0;
     yd = valid ? a.y[pi] : 0.0;
     zd = valid ? a.z[pi] : 0.0;
@@ -214,171 +406,66 @@ __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coe
 
   int tcount = 0;
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    // ---------------- phase 1: basis of the tile's particles (one per lane)
-    if (lane < a.tp) {
-      const Sph<T> s = sph<T>(xd, yd, zd);
-      const T tu = s.t * s.u, ctu = s.ct * tu, tu2 = tu * tu, stu = s.st * tu;
-      T* Gp = G + lane * SPG;
-      T* Zp = Z + lane * SPZ;
-      // angular jobs: column m of mass u (tu)^l Ybar_lm (cos, sin)(m phi), l = m..lmax.
-      // The diagonal value mass u (tu)^m Ybar_mm and (cos, sin)(m phi) are walked up
-      // to the largest column this wavefront owns.
-      T Pd = T(md) * s.u * T(kTab.c1[0][0]);
-      T cmc = T(1), smc = T(0);
-      static_for<LB + 1>([&](auto mc) {
-        constexpr int m = decltype(mc)::value;
-        if constexpr (m > 0) {
-          if (m <= maxm_w) {
-            Pd = (T(kTab.c1[m][m]) * stu) * Pd;
-            const T c2 = cmc * s.cp - smc * s.sp;
-            smc = smc * s.cp + cmc * s.sp;
-            cmc = c2;
-          }
-        }
-        if (wave == kJP.ownerZ[m] && m <= lmax) {
-          constexpr int sc = m == 0 ? 0 : 2 * m - 1;
-          T P2 = T(0), P1 = Pd;
-          Zp[zoff(m, BS) + sc] = P1 * cmc;
-          if constexpr (m > 0) Zp[zoff(m, BS) + sc + 1] = P1 * smc;
-          static_for<LB - m>([&](auto kc) {
-            constexpr int l = m + 1 + decltype(kc)::value;
-            if (l <= lmax) {
-              const T P = (T(kTab.c1[l][m]) * ctu) * P1 - (T(kTab.c2[l][m]) * tu2) * P2;
-              P2 = P1;
-              P1 = P;
-              Zp[zoff(l, BS) + sc] = P * cmc;
-              if constexpr (m > 0) Zp[zoff(l, BS) + sc + 1] = P * smc;
-            }
-          });
-        }
-      });
-      // radial jobs: monic Gegenbauer Chat_n^(2l+3/2)(xi), n = 0..NRP-1.  Entries past
-      // nmax only feed coefficients that are never written out; they stay finite.
-      static_for<LB + 1>([&](auto lc) {
-        constexpr int l = decltype(lc)::value;
-        if (wave == kJP.ownerG[l] && l <= lmax) {
-          T p2 = T(1), p1 = T(0);
-          static_for<NRP / 4>([&](auto qc) {
-            constexpr int nb4 = 4 * decltype(qc)::value;
-            T v[4];
-            static_for<4>([&](auto jc) {
-              constexpr int nn = nb4 + decltype(jc)::value;
-              const T c = s.xi * p1 - T(kTab.q[l][nn]) * p2;
-              p2 = p1;
-              p1 = c;
-              v[decltype(jc)::value] = c;
-            });
-            T* row = Gp + l * NRP + nb4;
-            if constexpr (sizeof(T) == 4) {
-              *reinterpret_cast<float4*>(row) = make_float4(v[0], v[1], v[2], v[3]);
-            } else {
-              *reinterpret_cast<double2*>(row) = make_double2(v[0], v[1]);
-              *reinterpret_cast<double2*>(row + 2) = make_double2(v[2], v[3]);
-            }
-          });
-        }
-      });
-    }
+    w.phase1(xd, yd, zd, md);
     __syncthreads();
-    // next tile's particles load while phase 2 runs
-    load_particle(tile + gridDim.x);
-
-    // ---------------- phase 2: outer-product accumulation over the tile
-    if (active) {
-      const T* gbase = G + bl * NRP + n0;
-      const T* zbase = Z + zoff_rt<BS>(bl) + s0;
-      constexpr int NG = (NB + 3) / 4 * 4;
-      T gv[2][NG], zv[2][BS];
-      auto fetch = [&](int p, int buf) {
-        const T* g = gbase + p * SPG;
-        const T* zz = zbase + p * SPZ;
-        if constexpr (sizeof(T) == 4) {
-#pragma unroll
-          for (int q = 0; q < NG / 4; ++q) {
-            const float4 f = reinterpret_cast<const float4*>(g)[q];
-            gv[buf][4 * q] = f.x;
-            gv[buf][4 * q + 1] = f.y;
-            gv[buf][4 * q + 2] = f.z;
-            gv[buf][4 * q + 3] = f.w;
-          }
-        } else {
-#pragma unroll
-          for (int q = 0; q < (NB + 1) / 2; ++q) {
-            const double2 f = reinterpret_cast<const double2*>(g)[q];
-            gv[buf][2 * q] = f.x;
-            gv[buf][2 * q + 1] = f.y;
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < BS; ++j) zv[buf][j] = zz[j];
-      };
-      auto madd = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int j = 0; j < BS; ++j) acc[i][j] = fma_(gv[buf][i], zv[buf][j], acc[i][j]);
-      };
-      // two particles per trip, each one's LDS reads issued before the other's FMAs
-      int p = my_stream;
-      if (p < a.tp) fetch(p, 0);
-      for (; p + a.streams < a.tp; p += 2 * a.streams) {
-        fetch(p + a.streams, 1);
-        madd(0);
-        if (p + 2 * a.streams < a.tp) fetch(p + 2 * a.streams, 0);
-        madd(1);
-      }
-      if (p < a.tp) madd(0);
-    }
+    load_particle(tile + gridDim.x);  // next tile's particles load while phase 2 runs
+    w.phase2();
     if (++tcount == a.flush_tiles) {
       tcount = 0;
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int j = 0; j < BS; ++j) {
-          wide[i][j].add(acc[i][j]);
-          acc[i][j] = T(0);
-        }
+      w.fold();
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < BS; ++j) wide[i][j].add(acc[i][j]);
+  w.fold();
+  using PT = typename CoeffWG<T, LB, NB, BS, MODE>::PT;
+  w.merge_write(lds_raw, reinterpret_cast<PT*>(a.partials) + size_t(blockIdx.x) * 2 * a.K, a.K);
+}
 
-  // ---------------- merge the streams in a fixed order through LDS
-  using PT = typename PartialT<(sizeof(T) == 4 && MODE == 1) ? 1 : 0>::type;
-  PT* out = reinterpret_cast<PT*>(lds_raw);
-  for (int s = 0; s < a.streams; ++s) {
-    if (active && my_stream == s) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int j = 0; j < BS; ++j) {
-          const int e = (my_block * NB + i) * BS + j;
-          const PT v = wide_value(wide[i][j]);
-          out[e] = (s == 0) ? v : merge(out[e], v);
-        }
-    }
+// Batched systems: the work is cut into units of at most kUnitParticles particles of
+// one system (unit u of system s covers its particles from (u - ustart[s]) *
+// kUnitParticles on); each unit's sums go to their own partial slot, so the per-system
+// reduction below has a fixed order whatever the schedule.
+struct BatchedCoeffArgs {
+  const double *x, *y, *z, *m;
+  const int64_t* offsets;
+  const int* ustart;  // [nsys+1] first unit of each system; ustart[nsys] = number of units
+  const int* usys;    // [units] system of each unit
+  int64_t ntotal;
+  void* partials;     // [units][2K]
+  int nsys, K, nmax, lmax, tp, nblocks, streams, nchunks;
+};
+
+template <typename T, int LB, int NB, int BS, int MODE>
+__global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coeff_batched_kernel(
+    const BatchedCoeffArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  using W = CoeffWG<T, LB, NB, BS, MODE>;
+  W w;
+  w.init(lds_raw, a.tp, a.lmax, a.nmax, a.nblocks, a.streams, a.nchunks);
+  const int nunits = a.ustart[a.nsys];
+  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+    const int s = a.usys[u];
+    int64_t b = a.offsets[s], e = a.offsets[s + 1];
+    b = b < 0 ? 0 : (b > a.ntotal ? a.ntotal : b);
+    e = e < b ? b : (e > a.ntotal ? a.ntotal : e);
+    const int64_t ub = b + int64_t(u - a.ustart[s]) * kUnitParticles;
+    const int64_t ue = ub + kUnitParticles < e ? ub + kUnitParticles : e;
+    const int ntiles = int((ue - ub + a.tp - 1) / a.tp);
+    w.zero_slots();
+    w.clear_wide();
     __syncthreads();
-  }
-
-  // ---------------- write this workgroup's partial sums, coefficient layout
-  PT* part = reinterpret_cast<PT*>(a.partials) + size_t(blockIdx.x) * 2 * a.K;
-  const int L2 = (lmax + 1) * (lmax + 2) / 2;
-  const int nent = a.nblocks * NB * BS;
-  for (int e = tid; e < nent; e += kCoeffThreads) {
-    const int j = e % BS;
-    const int i = (e / BS) % NB;
-    int l, nb0, sb0;
-    decode_block<NB, BS>(e / (NB * BS), lmax, a.nchunks, l, nb0, sb0);
-    const int nn = nb0 + i;
-    const int slot = sb0 + j;
-    if (nn > nmax || slot > 2 * l) continue;
-    const int m = (slot + 1) / 2;
-    const bool is_sin = slot > 0 && (slot & 1) == 0;
-    const int k = nn * L2 + l * (l + 1) / 2 + m;
-    part[(is_sin ? a.K : 0) + k] = out[e];
+    for (int tile = 0; tile < ntiles; ++tile) {
+      const int64_t pi = ub + int64_t(tile) * a.tp + w.lane;
+      const bool valid = w.lane < a.tp && pi < ue;
+      w.phase1(valid ? a.x[pi] : 0.0, valid ? a.y[pi] : 0.0, valid ? a.z[pi] : 0.0,
+               valid ? a.m[pi] : 0.0);
+      __syncthreads();
+      w.phase2();
+      __syncthreads();
+    }
+    w.fold();
+    w.merge_write(lds_raw, reinterpret_cast<typename W::PT*>(a.partials) + size_t(u) * 2 * a.K, a.K);
+    __syncthreads();
   }
 }
 
@@ -476,37 +563,62 @@ double anl_tilde(int n, int l) {
 
 namespace {
 
-template <typename T, int LB, int NB, int BS, int MODE>
-int launch_coeff_t(const CoeffPlan& p, const CoeffArgs& a, hipStream_t st) {
-  auto kfn = scf_coeff_kernel<T, LB, NB, BS, MODE>;
+template <bool BATCHED, typename T, int LB, int NB, int BS, int MODE, typename Args>
+int launch_coeff_t(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
+  const void* kfn;
+  if constexpr (BATCHED)
+    kfn = reinterpret_cast<const void*>(scf_coeff_batched_kernel<T, LB, NB, BS, MODE>);
+  else
+    kfn = reinterpret_cast<const void*>(scf_coeff_kernel<T, LB, NB, BS, MODE>);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    // the kernel has no static LDS: the whole 160 KiB of a CU may be requested
+    hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(scf_coeff)");
     attr_set = true;
   }
-  hipLaunchKernelGGL(kfn, dim3(p.grid), dim3(kCoeffThreads), p.lds_bytes, st, a);
+  if constexpr (BATCHED)
+    hipLaunchKernelGGL((scf_coeff_batched_kernel<T, LB, NB, BS, MODE>), dim3(grid), dim3(kCoeffThreads),
+                       p.lds_bytes, st, a);
+  else
+    hipLaunchKernelGGL((scf_coeff_kernel<T, LB, NB, BS, MODE>), dim3(grid), dim3(kCoeffThreads),
+                       p.lds_bytes, st, a);
   return hip_fail(hipGetLastError(), "scf_coeff_kernel launch");
 }
 
-template <typename T, int MODE, int LB>
-int launch_coeff_nb(const CoeffPlan& p, const CoeffArgs& a, hipStream_t st) {
+template <bool BATCHED, typename T, int MODE, int LB, typename Args>
+int launch_coeff_nb(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
   switch (p.nb) {
-    case 9: return launch_coeff_t<T, LB, 9, 4, MODE>(p, a, st);
-    case 11: return launch_coeff_t<T, LB, 11, 4, MODE>(p, a, st);
-    default: return launch_coeff_t<T, LB, 12, 4, MODE>(p, a, st);
+    case 9: return launch_coeff_t<BATCHED, T, LB, 9, 4, MODE>(p, a, grid, st);
+    case 11: return launch_coeff_t<BATCHED, T, LB, 11, 4, MODE>(p, a, grid, st);
+    default: return launch_coeff_t<BATCHED, T, LB, 12, 4, MODE>(p, a, grid, st);
   }
 }
 
-template <typename T, int MODE>
-int launch_coeff_lb(const CoeffPlan& p, const CoeffArgs& a, hipStream_t st) {
-  switch (p.lb) {
-    case 2: return launch_coeff_nb<T, MODE, 2>(p, a, st);
-    case 6: return launch_coeff_nb<T, MODE, 6>(p, a, st);
-    case 10: return launch_coeff_nb<T, MODE, 10>(p, a, st);
-    default: return launch_coeff_nb<T, MODE, 14>(p, a, st);
+template <bool BATCHED, typename Args>
+int launch_coeff_any(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
+  const int mode = p.prec == ETICS_FP64 ? 0 : (p.prec == ETICS_MIXED_FP64ACC ? 1 : 2);
+#define ETICS_LB_CASES(T, MODE)                                                  \
+  switch (p.lb) {                                                                \
+    case 2: return launch_coeff_nb<BATCHED, T, MODE, 2>(p, a, grid, st);         \
+    case 6: return launch_coeff_nb<BATCHED, T, MODE, 6>(p, a, grid, st);         \
+    case 10: return launch_coeff_nb<BATCHED, T, MODE, 10>(p, a, grid, st);       \
+    default: return launch_coeff_nb<BATCHED, T, MODE, 14>(p, a, grid, st);       \
   }
+  if (mode == 0) {
+    ETICS_LB_CASES(double, 0)
+  } else if (mode == 1) {
+    ETICS_LB_CASES(float, 0)
+  } else {
+    ETICS_LB_CASES(float, 1)
+  }
+#undef ETICS_LB_CASES
+}
+
+void fill_scale(double* scale, int nmax, int lmax) {
+  for (int nn = 0; nn <= nmax; ++nn)
+    for (int l = 0; l <= lmax; ++l)
+      scale[nn * (lmax + 1) + l] = -2.0 * std::sqrt(kPi) * anl_tilde(nn, l) * gegen_k(nn, 2.0 * l + 1.5);
 }
 
 }  // namespace
@@ -581,14 +693,8 @@ int launch_scf_coeffs(const CoeffPlan& p, const double* x, const double* y, cons
   a.ntiles = int((n + p.tp - 1) / p.tp);
   a.nchunks = p.nchunks;
 
-  int rc;
   const int mode = p.prec == ETICS_FP64 ? 0 : (p.prec == ETICS_MIXED_FP64ACC ? 1 : 2);
-  if (mode == 0)
-    rc = launch_coeff_lb<double, 0>(p, a, st);
-  else if (mode == 1)
-    rc = launch_coeff_lb<float, 0>(p, a, st);
-  else
-    rc = launch_coeff_lb<float, 1>(p, a, st);
+  int rc = launch_coeff_any<false>(p, a, p.grid, st);
   if (rc) return rc;
 
   ReduceArgs r{};
@@ -599,16 +705,109 @@ int launch_scf_coeffs(const CoeffPlan& p, const double* x, const double* y, cons
   r.K = K;
   r.nmax = p.nmax;
   r.lmax = p.lmax;
-  for (int nn = 0; nn <= p.nmax; ++nn)
-    for (int l = 0; l <= p.lmax; ++l)
-      r.scale[nn * (p.lmax + 1) + l] =
-          -2.0 * std::sqrt(kPi) * anl_tilde(nn, l) * gegen_k(nn, 2.0 * l + 1.5);
+  fill_scale(r.scale, p.nmax, p.lmax);
   const int rb = (2 * K + kRedCols - 1) / kRedCols;
   if (mode == 2)
     hipLaunchKernelGGL(scf_reduce_kernel<1>, dim3(rb), dim3(256), 0, st, r);
   else
     hipLaunchKernelGGL(scf_reduce_kernel<0>, dim3(rb), dim3(256), 0, st, r);
   return hip_fail(hipGetLastError(), "scf_reduce_kernel launch");
+}
+
+// ------------------------------------------------------------ batched reduce
+struct BatchedReduceArgs {
+  const void* partials;  // [units][2K]
+  const int* ustart;     // [nsys+1]
+  double* A;             // [nsys*K]
+  double* B;
+  int nsys, K, nmax, lmax;
+  double scale[(NCAP + 1) * (LCAP + 1)];
+};
+
+// one workgroup per system: its units' partials summed in unit order
+template <int MODE>
+__global__ __launch_bounds__(256) void scf_reduce_batched_kernel(const BatchedReduceArgs a) {
+  using PT = typename PartialT<MODE>::type;
+  const int s = blockIdx.x;
+  const int u0 = a.ustart[s], u1 = a.ustart[s + 1];
+  const size_t stride = size_t(2) * a.K;
+  const int L2 = (a.lmax + 1) * (a.lmax + 2) / 2;
+  for (int c = threadIdx.x; c < 2 * a.K; c += blockDim.x) {
+    const int k = c < a.K ? c : c - a.K;
+    const int n = k / L2;
+    const int lm = k - n * L2;
+    int l = 0;
+    while ((l + 1) * (l + 2) / 2 <= lm) ++l;
+    const int m = lm - l * (l + 1) / 2;
+    const bool is_sin = c >= a.K;
+    double* dst = (is_sin ? a.B : a.A) + size_t(s) * a.K + k;
+    if (is_sin && m == 0) {
+      *dst = 0.0;
+      continue;
+    }
+    const PT* p = reinterpret_cast<const PT*>(a.partials) + c;
+    double v;
+    if constexpr (MODE == 0) {
+      double acc = 0.0;
+      for (int u = u0; u < u1; ++u) acc += p[size_t(u) * stride];
+      v = acc;
+    } else {
+      float2 acc = make_float2(0.f, 0.f);
+      for (int u = u0; u < u1; ++u) acc = merge(acc, p[size_t(u) * stride]);
+      v = double(acc.x) + double(acc.y);
+    }
+    *dst = (m == 0 ? 1.0 : 2.0) * a.scale[n * (a.lmax + 1) + l] * v;
+  }
+}
+
+int max_units(int64_t ntotal, int nsys) {
+  return nsys + int((ntotal + kUnitParticles - 1) / kUnitParticles);
+}
+
+int launch_scf_coeffs_batched(const CoeffPlan& p, const double* x, const double* y, const double* z,
+                              const double* m, const int64_t* offsets, const int* ustart,
+                              const int* usys, int nsys, int64_t ntotal, double* A, double* B,
+                              void* partials, hipStream_t st) {
+  const int K = coeff_count(p.nmax, p.lmax);
+  BatchedCoeffArgs a{};
+  a.x = x;
+  a.y = y;
+  a.z = z;
+  a.m = m;
+  a.offsets = offsets;
+  a.ustart = ustart;
+  a.usys = usys;
+  a.ntotal = ntotal;
+  a.partials = partials;
+  a.nsys = nsys;
+  a.K = K;
+  a.nmax = p.nmax;
+  a.lmax = p.lmax;
+  a.tp = p.tp;
+  a.nblocks = p.nblocks;
+  a.streams = p.streams;
+  a.nchunks = p.nchunks;
+  const int wg_per_cu = (p.prec != ETICS_FP64 && p.lds_bytes <= 80 * 1024) ? 2 : 1;
+  int grid = 256 * wg_per_cu;
+  const int mu = max_units(ntotal, nsys);
+  if (grid > mu) grid = mu;
+  int rc = launch_coeff_any<true>(p, a, grid, st);
+  if (rc) return rc;
+  BatchedReduceArgs r{};
+  r.partials = partials;
+  r.ustart = ustart;
+  r.A = A;
+  r.B = B;
+  r.nsys = nsys;
+  r.K = K;
+  r.nmax = p.nmax;
+  r.lmax = p.lmax;
+  fill_scale(r.scale, p.nmax, p.lmax);
+  if (p.prec == ETICS_MIXED_COMP32)
+    hipLaunchKernelGGL(scf_reduce_batched_kernel<1>, dim3(nsys), dim3(256), 0, st, r);
+  else
+    hipLaunchKernelGGL(scf_reduce_batched_kernel<0>, dim3(nsys), dim3(256), 0, st, r);
+  return hip_fail(hipGetLastError(), "scf_reduce_batched_kernel launch");
 }
 
 }  // namespace etics

@@ -38,10 +38,13 @@ __device__ __forceinline__ const BasisTables<double>& tab<double>() { return g_t
 template <typename T>
 __global__ __launch_bounds__(256) void scf_force_prep_kernel(const double* __restrict__ A,
                                                             const double* __restrict__ B,
-                                                            int nmax, int lmax, T* __restrict__ cf) {
+                                                            int nmax, int lmax, int nsys,
+                                                            T* __restrict__ cf) {
   const int K = (nmax + 1) * (lmax + 1) * (lmax + 2) / 2;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= int64_t(nsys) * K) return;
+  const int sys = int(g / K);
+  const int k = int(g - int64_t(sys) * K);
   const int L2 = (lmax + 1) * (lmax + 2) / 2;
   const int n = k / L2;
   const int lm = k - n * L2;
@@ -51,10 +54,12 @@ __global__ __launch_bounds__(256) void scf_force_prep_kernel(const double* __res
   const double s4 = -2.0 * sqrt(kPi);
   const double su = s4 * gegen_k(n, al);
   const double sw = n >= 1 ? s4 * 4.0 * al * gegen_k(n - 1, al + 1.0) : 0.0;
-  cf[k] = T(su * A[k]);
-  cf[K + k] = T(su * B[k]);
-  cf[2 * K + k] = T(sw * A[k]);
-  cf[3 * K + k] = T(sw * B[k]);
+  const double a = A[g], b = B[g];
+  T* c = cf + size_t(sys) * 4 * K;
+  c[k] = T(su * a);
+  c[K + k] = T(su * b);
+  c[2 * K + k] = T(sw * a);
+  c[3 * K + k] = T(sw * b);
 }
 
 // ------------------------------------------------------------------------ force
@@ -67,16 +72,16 @@ struct ForceArgs {
   int want_pot;
 };
 
+// potential / acceleration of point i from one system's prepared coefficients cf
 template <typename T, int LB, bool ACC>
-__global__ __launch_bounds__(256) void scf_force_kernel(const ForceArgs a) {
+__device__ __forceinline__ void force_point(const ForceArgs& a, const T* __restrict__ cf,
+                                            int64_t i) {
   const BasisTables<T>& tb = tab<T>();
-  const T* __restrict__ cf = reinterpret_cast<const T*>(a.cf);
   const int K = a.K;
   const int L2 = (a.lmax + 1) * (a.lmax + 2) / 2;
   const int lmax = a.lmax;
   const int nmax = a.nmax;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
-       i += int64_t(gridDim.x) * blockDim.x) {
+  {
     const Sph<T> s = sph<T>(a.x[i], a.y[i], a.z[i]);
     const T tu = s.t * s.u, u2 = s.u * s.u;
 
@@ -225,71 +230,140 @@ __global__ __launch_bounds__(256) void scf_force_kernel(const ForceArgs a) {
   }
 }
 
+template <typename T, int LB, bool ACC>
+__global__ __launch_bounds__(256) void scf_force_kernel(const ForceArgs a) {
+  const T* __restrict__ cf = reinterpret_cast<const T*>(a.cf);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    force_point<T, LB, ACC>(a, cf, i);
+}
+
+// batched systems: one workgroup per unit of one system, so the coefficient pointer
+// (and with it every coefficient operand) is uniform across the workgroup
+template <typename T, int LB, bool ACC>
+__global__ __launch_bounds__(256) void scf_force_batched_kernel(const ForceArgs a,
+                                                                const int64_t* __restrict__ offsets,
+                                                                const int* __restrict__ ustart,
+                                                                const int* __restrict__ usys,
+                                                                int nsys) {
+  const int u = blockIdx.x;
+  if (u >= ustart[nsys]) return;
+  const int sys = usys[u];
+  int64_t b = offsets[sys], e = offsets[sys + 1];
+  b = b < 0 ? 0 : (b > a.n ? a.n : b);
+  e = e < b ? b : (e > a.n ? a.n : e);
+  const int64_t ub = b + int64_t(u - ustart[sys]) * kUnitParticles;
+  const int64_t ue = ub + kUnitParticles < e ? ub + kUnitParticles : e;
+  const T* __restrict__ cf = reinterpret_cast<const T*>(a.cf) + size_t(sys) * 4 * a.K;
+  for (int64_t i = ub + threadIdx.x; i < ue; i += blockDim.x) force_point<T, LB, ACC>(a, cf, i);
+}
+
 size_t force_prep_bytes(int nmax, int lmax, int prec) {
   return size_t(4) * coeff_count(nmax, lmax) * (prec == ETICS_FP64 ? 8 : 4);
 }
 
 namespace {
+
+struct BatchInfo {
+  const int64_t* offsets;
+  const int* ustart;
+  const int* usys;
+  int nsys;
+};
+
+template <typename T, bool ACC, int LBV>
+void launch_force_kernel(const ForceArgs& a, int grid, const BatchInfo* bi, hipStream_t st) {
+  if (bi)
+    hipLaunchKernelGGL((scf_force_batched_kernel<T, LBV, ACC>), dim3(grid), dim3(256), 0, st, a,
+                       bi->offsets, bi->ustart, bi->usys, bi->nsys);
+  else
+    hipLaunchKernelGGL((scf_force_kernel<T, LBV, ACC>), dim3(grid), dim3(256), 0, st, a);
+}
+
 template <typename T, bool ACC>
-int launch_force_lb(int lb, const ForceArgs& a, int grid, hipStream_t st) {
-#define ETICS_FORCE_CASE(LBV)                                                         \
-  case LBV:                                                                           \
-    hipLaunchKernelGGL((scf_force_kernel<T, LBV, ACC>), dim3(grid), dim3(256), 0, st, a); \
-    break;
+int launch_force_lb(int lb, const ForceArgs& a, int grid, const BatchInfo* bi, hipStream_t st) {
   switch (lb) {
-    ETICS_FORCE_CASE(2)
-    ETICS_FORCE_CASE(4)
-    ETICS_FORCE_CASE(6)
-    ETICS_FORCE_CASE(8)
-    ETICS_FORCE_CASE(10)
-    ETICS_FORCE_CASE(12)
-    ETICS_FORCE_CASE(14)
+    case 2: launch_force_kernel<T, ACC, 2>(a, grid, bi, st); break;
+    case 4: launch_force_kernel<T, ACC, 4>(a, grid, bi, st); break;
+    case 6: launch_force_kernel<T, ACC, 6>(a, grid, bi, st); break;
+    case 8: launch_force_kernel<T, ACC, 8>(a, grid, bi, st); break;
+    case 10: launch_force_kernel<T, ACC, 10>(a, grid, bi, st); break;
+    case 12: launch_force_kernel<T, ACC, 12>(a, grid, bi, st); break;
+    case 14: launch_force_kernel<T, ACC, 14>(a, grid, bi, st); break;
     default:
       set_error("internal: no force kernel bucket");
       return ETICS_EUNSUPPORTED;
   }
-#undef ETICS_FORCE_CASE
   return hip_fail(hipGetLastError(), "scf_force_kernel launch");
 }
-}  // namespace
 
-int launch_scf_force(const double* x, const double* y, const double* z, int64_t n, int nmax,
-                     int lmax, const double* A, const double* B, int prec, int outputs,
-                     double* pot, double* ax, double* ay, double* az, void* ws, hipStream_t st) {
+int launch_prep(const double* A, const double* B, int nmax, int lmax, int nsys, int prec, void* ws,
+                hipStream_t st) {
   const int K = coeff_count(nmax, lmax);
-  const bool f64 = prec == ETICS_FP64;
-  const int pb = (K + 255) / 256;
-  if (f64)
+  const int pb = int((int64_t(nsys) * K + 255) / 256);
+  if (prec == ETICS_FP64)
     hipLaunchKernelGGL(scf_force_prep_kernel<double>, dim3(pb), dim3(256), 0, st, A, B, nmax, lmax,
-                       reinterpret_cast<double*>(ws));
+                       nsys, reinterpret_cast<double*>(ws));
   else
     hipLaunchKernelGGL(scf_force_prep_kernel<float>, dim3(pb), dim3(256), 0, st, A, B, nmax, lmax,
-                       reinterpret_cast<float*>(ws));
-  int rc = hip_fail(hipGetLastError(), "scf_force_prep_kernel launch");
-  if (rc || n == 0) return rc;
+                       nsys, reinterpret_cast<float*>(ws));
+  return hip_fail(hipGetLastError(), "scf_force_prep_kernel launch");
+}
+
+int launch_force_any(const ForceArgs& a, int prec, int outputs, int grid, const BatchInfo* bi,
+                     hipStream_t st) {
+  const int lb = a.lmax <= 2 ? 2 : (a.lmax + 1) / 2 * 2;
+  const bool acc = (outputs & ETICS_ACC) != 0;
+  if (prec == ETICS_FP64)
+    return acc ? launch_force_lb<double, true>(lb, a, grid, bi, st)
+               : launch_force_lb<double, false>(lb, a, grid, bi, st);
+  return acc ? launch_force_lb<float, true>(lb, a, grid, bi, st)
+             : launch_force_lb<float, false>(lb, a, grid, bi, st);
+}
+
+ForceArgs make_force_args(const double* x, const double* y, const double* z, int64_t n, int nmax,
+                          int lmax, int outputs, double* pot, double* ax, double* ay, double* az,
+                          const void* cf) {
   ForceArgs a{};
   a.x = x;
   a.y = y;
   a.z = z;
   a.n = n;
-  a.cf = ws;
+  a.cf = cf;
   a.pot = pot;
   a.ax = ax;
   a.ay = ay;
   a.az = az;
-  a.K = K;
+  a.K = coeff_count(nmax, lmax);
   a.nmax = nmax;
   a.lmax = lmax;
   a.want_pot = (outputs & ETICS_POT) ? 1 : 0;
-  const int lb = lmax <= 2 ? 2 : (lmax + 1) / 2 * 2;
+  return a;
+}
+
+}  // namespace
+
+int launch_scf_force(const double* x, const double* y, const double* z, int64_t n, int nmax,
+                     int lmax, const double* A, const double* B, int prec, int outputs,
+                     double* pot, double* ax, double* ay, double* az, void* ws, hipStream_t st) {
+  int rc = launch_prep(A, B, nmax, lmax, 1, prec, ws, st);
+  if (rc || n == 0) return rc;
+  const ForceArgs a = make_force_args(x, y, z, n, nmax, lmax, outputs, pot, ax, ay, az, ws);
   int64_t grid = (n + 255) / 256;
   if (grid > 65536) grid = 65536;
-  const bool acc = (outputs & ETICS_ACC) != 0;
-  if (f64)
-    return acc ? launch_force_lb<double, true>(lb, a, int(grid), st)
-               : launch_force_lb<double, false>(lb, a, int(grid), st);
-  return acc ? launch_force_lb<float, true>(lb, a, int(grid), st)
-             : launch_force_lb<float, false>(lb, a, int(grid), st);
+  return launch_force_any(a, prec, outputs, int(grid), nullptr, st);
+}
+
+int launch_scf_force_batched(const double* x, const double* y, const double* z,
+                             const int64_t* offsets, const int* ustart, const int* usys, int nsys,
+                             int64_t ntotal, int nmax, int lmax, const double* A, const double* B,
+                             int prec, int outputs, double* pot, double* ax, double* ay,
+                             double* az, void* prep, hipStream_t st) {
+  int rc = launch_prep(A, B, nmax, lmax, nsys, prec, prep, st);
+  if (rc || ntotal == 0) return rc;
+  const ForceArgs a = make_force_args(x, y, z, ntotal, nmax, lmax, outputs, pot, ax, ay, az, prep);
+  const BatchInfo bi{offsets, ustart, usys, nsys};
+  return launch_force_any(a, prec, outputs, max_units(ntotal, nsys), &bi, st);
 }
 
 }  // namespace etics

@@ -24,6 +24,7 @@ inline int coeff_count(int nmax, int lmax) { return (nmax + 1) * lm_count(lmax);
 constexpr int kCoeffThreads = 256;  // 4 wavefronts
 constexpr int kMaxJobs = 32;        // basis jobs per wavefront (2 (lmax+1) <= 30)
 constexpr int kMaxStreams = 32;
+constexpr int kUnitParticles = 1024;  // batched work unit: particles of one system
 
 struct CoeffPlan {
   int nmax, lmax, prec;   // prec: ETICS_* precision mode
@@ -50,6 +51,29 @@ int launch_scf_coeffs(const CoeffPlan& p, const double* x, const double* y, cons
 int launch_scf_force(const double* x, const double* y, const double* z, int64_t n, int nmax,
                      int lmax, const double* A, const double* B, int prec, int outputs,
                      double* pot, double* ax, double* ay, double* az, void* ws, hipStream_t st);
+
+int max_units(int64_t ntotal, int nsys);
+int launch_scf_coeffs_batched(const CoeffPlan& p, const double* x, const double* y, const double* z,
+                              const double* m, const int64_t* offsets, const int* ustart,
+                              const int* usys, int nsys, int64_t ntotal, double* A, double* B,
+                              void* partials, hipStream_t st);
+int launch_scf_force_batched(const double* x, const double* y, const double* z,
+                             const int64_t* offsets, const int* ustart, const int* usys, int nsys,
+                             int64_t ntotal, int nmax, int lmax, const double* A, const double* B,
+                             int prec, int outputs, double* pot, double* ax, double* ay,
+                             double* az, void* prep, hipStream_t st);
+
+struct BatchedLayout {
+  size_t off_ustart, off_usys, off_partials, off_prep, off_A, off_B, off_acc, total;
+  int max_units;
+};
+BatchedLayout batched_layout(int64_t ntotal, int nsys, int nmax, int lmax, int prec);
+int launch_units(const int64_t* offsets, int nsys, int64_t ntotal, int* ustart, int* usys,
+                 hipStream_t st);
+int run_leapfrog(double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                 const double* m, const int64_t* offsets, int nsys, int64_t ntotal, int nmax,
+                 int lmax, int prec, double dt, int nsteps, int flags, void* ws, size_t ws_bytes,
+                 hipStream_t st);
 
 size_t mex_ws_bytes(int64_t n, int lmax);
 int launch_mex_force(const double* x, const double* y, const double* z, const double* m, int64_t n,

@@ -494,10 +494,10 @@ int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(mex_tile_sums_kernel<T, LB>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e == hipSuccess)
       e = hipFuncSetAttribute(reinterpret_cast<const void*>(mex_force_kernel<T, LB>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(mex)");
     attr_set = true;
   }

@@ -25,6 +25,7 @@ ETICS_MIXED_COMP32 = 2
 ETICS_POT = 1
 ETICS_ACC = 2
 ETICS_POT_ACC = 3
+ETICS_LEAPFROG_EAGER = 1
 ETICS_NMAX_CAP = 20
 ETICS_LMAX_CAP = 14
 
@@ -81,7 +82,8 @@ def lib():
                                               _int, _int, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
         L.etics_scf_force_batched.restype = _int
         L.etics_leapfrog_scf_batched.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _int, _i64,
-                                                 _int, _int, _int, ctypes.c_double, _int, _vp, _sz, _vp]
+                                                 _int, _int, _int, ctypes.c_double, _int, _int, _vp, _sz,
+                                                 _vp]
         L.etics_leapfrog_scf_batched.restype = _int
         L.etics_last_error.restype = ctypes.c_char_p
         L.etics_version.restype = ctypes.c_char_p
@@ -244,7 +246,8 @@ def etics_scf_force_batched(x, y, z, offsets, nmax: int, lmax: int, A, B, precis
 
 
 def etics_leapfrog_scf_batched(x, y, z, vx, vy, vz, m, offsets, nmax: int, lmax: int, dt: float,
-                               nsteps: int, precision=ETICS_MIXED_FP64ACC, ws=None, stream=None):
+                               nsteps: int, precision=ETICS_MIXED_FP64ACC, flags: int = 0, ws=None,
+                               stream=None):
     """Advance x..vz in place by nsteps KDK steps (one captured graph replayed)."""
     p = _prec(precision)
     _dev(offsets, "offsets", torch.int64)
@@ -254,4 +257,4 @@ def etics_leapfrog_scf_batched(x, y, z, vx, vy, vz, m, offsets, nmax: int, lmax:
     ws = workspace(need, x.device) if ws is None else ws
     _check(lib().etics_leapfrog_scf_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz),
                                             _ptr(m), _ptr(offsets), nsys, n, nmax, lmax, p, float(dt),
-                                            int(nsteps), _ptr(ws), ws.numel(), _stream(stream)))
+                                            int(nsteps), int(flags), _ptr(ws), ws.numel(), _stream(stream)))

@@ -145,9 +145,10 @@ def test_output_modes_agree(E):
     both = gpu_force(E, p, 8, 6, A, B, MIXED, 3)
     pot = gpu_force(E, p, 8, 6, A, B, MIXED, 1)
     accel = gpu_force(E, p, 8, 6, A, B, MIXED, 2)
-    assert np.array_equal(pot[0], both[0])
+    # separate kernel instantiations may contract FMAs differently: equal to FP32 rounding
+    np.testing.assert_allclose(pot[0], both[0], rtol=1e-6)
     for k in (1, 2, 3):
-        assert np.array_equal(accel[k], both[k])
+        np.testing.assert_allclose(accel[k], both[k], rtol=1e-6, atol=1e-6 * np.max(np.abs(both[k])))
 
 
 def test_origin_and_axis_points(E, orc):
