@@ -10,13 +10,21 @@ the mixed mode (FP32 basis and synthesis, FP64 coefficient reduction); the plain
 FP64 path is timed beside it.  Accuracy of both is measured against the FP64 CPU
 oracle, which is also timed on the host as the CPU baseline.
 
+The main kernel of each call is bracketed by HIP events through
+etics_set_timing_events, on the stream the kernels run on; the roofline figure of the
+dominant kernel uses those durations.  Also timed (reported under "extras", not the
+headline): the MEX force of N = 10^6 (Plummer + Hernquist mixture, lmax = 10) and a
+hipGraph leapfrog step of 256 independent systems (about 5.5e6 particles, (8, 6)).
+
 Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -26,6 +34,13 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+CSRC = os.path.join(ROOT, "paper_1406_4254_amd", "csrc")
+KERNEL_SOURCES = {
+    "coeff": ["etics_coeff.hip", "etics_device.hpp", "etics_tables.hpp"],
+    "force": ["etics_force.hip", "etics_device.hpp", "etics_tables.hpp"],
+}
 
 
 def coeff_count(nmax, lmax):
@@ -49,6 +64,65 @@ def flops_per_particle(nmax, lmax):
     return coef, force
 
 
+def source_digest(which):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[which]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(which, workload):
+    """HBM bytes per launch from the committed counter summary of this kernel and
+    workload, or None if there is none or the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{which}_kernel_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        m = re.search(r"^traffic_json:\s*(\{.*\})\s*$", fh.read(), re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha256") != source_digest(which):
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def copy_calibration(torch, nbytes=256 << 20, reps=3):
+    """Plain device-to-device copies of a known size; a counter run over this program
+    reads them to scale the HBM byte counters."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+class KernelTimer:
+    """Pairs of events recorded around the main kernel of one call each."""
+
+    def __init__(self, torch, etics, count, stream):
+        self.etics = etics
+        self.pairs = []
+        for _ in range(count):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)  # creates the device events
+            b.record(stream)
+            self.pairs.append((a, b))
+        self.k = 0
+
+    def arm(self):
+        a, b = self.pairs[self.k]
+        self.k += 1
+        self.etics.etics_set_timing_events(a, b)
+
+    def mean_ms(self):
+        self.etics.etics_set_timing_events(None, None)
+        return sum(a.elapsed_time(b) for a, b in self.pairs[:self.k]) / max(self.k, 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +133,9 @@ def main():
     ap.add_argument("--lmax", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run plain 256 MiB device copies (for scaling byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -73,33 +150,41 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    nmax, lmax, n = args.nmax, args.lmax, args.n
-    p = workloads.triaxial_hernquist(n, seed=2)
-    dev = [torch.from_numpy(a).cuda() for a in (p.x, p.y, p.z, p.m)]
-    x, y, z, m = dev
-    K = coeff_count(nmax, lmax)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        copy_calibration(torch)
+
+    nmax, lmax, n = args.nmax, args.lmax, args.n
+    headline = (n, nmax, lmax) == (1_000_000, 10, 10)
+    workload = "scf_triaxial_hernquist_n1e6_n10_l10" if headline else f"scf_triaxial_hernquist_n{n}_n{nmax}_l{lmax}"
+    p = workloads.triaxial_hernquist(n, seed=2)
+    x, y, z, m = (torch.from_numpy(a).cuda() for a in (p.x, p.y, p.z, p.m))
+    K = coeff_count(nmax, lmax)
 
     def run_mode(prec, steps, warmup):
         A = torch.empty(K, dtype=torch.float64, device="cuda")
         B = torch.empty_like(A)
         pot, ax, ay, az = (torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(4))
         ws = etics.workspace(etics.etics_scf_workspace_size(n, nmax, lmax, prec), "cuda")
+        kc = KernelTimer(torch, etics, steps, stream)
+        kf = KernelTimer(torch, etics, steps, stream)
 
         def step(ev=None):
             if ev is not None:
                 ev[0].record(stream)
+                kc.arm()
             etics.etics_scf_coeffs(x, y, z, m, nmax, lmax, prec, A, B, ws, stream)
             if ev is not None:
                 ev[1].record(stream)
+                kf.arm()
             etics.etics_scf_force(x, y, z, nmax, lmax, A, B, prec, etics.ETICS_POT_ACC, pot, ax, ay, az,
                                   ws, stream)
             if ev is not None:
                 ev[2].record(stream)
+                etics.etics_set_timing_events(None, None)
 
         for _ in range(warmup):
             step()
-        torch.cuda.synchronize()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -107,32 +192,47 @@ def main():
             step(evs[k])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        coef_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-        force_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+        res = {
+            "wall_s": wall,
+            "coeff_call_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
+            "force_call_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in evs])),
+            "coeff_kernel_ms": kc.mean_ms(),
+            "force_kernel_ms": kf.mean_ms(),
+        }
         out = [t.cpu().numpy() for t in (A, B, pot, ax, ay, az)]
-        return wall, coef_ms, force_ms, out
+        return res, out
 
-    wall, coef_ms, force_ms, res = run_mode(etics.ETICS_MIXED_FP64ACC, args.steps, args.warmup)
-    ms_per_step = wall / args.steps * 1e3
-    value = n / (wall / args.steps)
+    mixed, res = run_mode(etics.ETICS_MIXED_FP64ACC, args.steps, args.warmup)
+    ms_per_step = mixed["wall_s"] / args.steps * 1e3
+    value = n / (mixed["wall_s"] / args.steps)
 
     fp64 = None
     if not args.no_fp64:
-        w64, c64, f64, res64 = run_mode(etics.ETICS_FP64, args.steps, args.warmup)
-        fp64 = {"value": n / (w64 / args.steps), "ms_per_step": w64 / args.steps * 1e3,
-                "coeff_call_ms": c64, "force_call_ms": f64}
+        r64, res64 = run_mode(etics.ETICS_FP64, args.steps, args.warmup)
+        fp64 = {"value": n / (r64["wall_s"] / args.steps), "ms_per_step": r64["wall_s"] / args.steps * 1e3,
+                **{k: v for k, v in r64.items() if k != "wall_s"}}
 
     fc, ff = flops_per_particle(nmax, lmax)
-    # dominant kernel: the force call (force kernel + a coefficient rescale of K entries)
-    dom = "force" if force_ms >= coef_ms else "coeff"
-    dom_ms = force_ms if dom == "force" else coef_ms
-    dom_flops = (ff if dom == "force" else fc) * n
-    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    lb_force = 2 if lmax <= 2 else (lmax + 1) // 2 * 2
+    lb_coeff = 2 if lmax <= 2 else (6 if lmax <= 6 else (10 if lmax <= 10 else 14))
+    nb = 9 if nmax + 1 <= 9 else (11 if nmax + 1 <= 11 else 12)
+    kernels = {
+        "force": (mixed["force_kernel_ms"], ff, f"scf_force_kernel<float,{lb_force},true>"),
+        "coeff": (mixed["coeff_kernel_ms"], fc, f"scf_coeff_kernel<float,{lb_coeff},{nb},4,0>"),
+    }
+    dom = max(kernels, key=lambda k: kernels[k][0])
+    dom_ms, dom_fpp, dom_name = kernels[dom]
+    achieved = dom_fpp * n / (dom_ms * 1e-3) / 1e12
+    traffic = measured_traffic(dom, workload)
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                "kernel": "scf_force_kernel<float,10,true>" if dom == "force" else "scf_coeff_kernel<float,11,4,0>",
-                "flops_per_particle": ff if dom == "force" else fc,
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
+                "kernel": dom_name, "kernel_ms": dom_ms, "flops_per_particle": dom_fpp,
+                "particles_per_launch": n,
                 "frac_of_nonpacked_fp32": achieved / (PEAK_FP32_VECTOR_TFLOPS / 2)}
+    if traffic is not None:
+        roofline["traffic_frac_of_hbm_peak"] = traffic / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBS
+    other = "coeff" if dom == "force" else "force"
+    o_ms, o_fpp, o_name = kernels[other]
     step_tflops = (fc + ff) * n / (ms_per_step * 1e-3) / 1e12
 
     out = {
@@ -148,20 +248,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "scf_triaxial_hernquist_n1e6_n10_l10" if (n, nmax, lmax) == (1_000_000, 10, 10)
-                   else f"scf_triaxial_hernquist_n{n}_n{nmax}_l{lmax}",
-                   "n": n, "nmax": nmax, "lmax": lmax, "seed": 2, "axes": [1.0, 0.8, 0.6],
-                   "precision": "mixed: fp32 basis/synthesis, fp64 reduction"},
-        "stages_ms": {"coeff_call": coef_ms, "force_call": force_ms},
+        "config": {"workload": workload, "n": n, "nmax": nmax, "lmax": lmax, "seed": 2,
+                   "axes": [1.0, 0.8, 0.6], "precision": "mixed: fp32 basis/synthesis, fp64 reduction"},
+        "stages_ms": {k: v for k, v in mixed.items() if k != "wall_s"},
         "step_tflops": step_tflops,
         "roofline": roofline,
+        "other_kernel": {"kernel": o_name, "kernel_ms": o_ms, "achieved": o_fpp * n / (o_ms * 1e-3) / 1e12,
+                         "unit": "TFLOP/s", "flops_per_particle": o_fpp},
     }
     if fp64:
         out["fp64"] = fp64
         out["speedup_vs_fp64"] = value / fp64["value"]
 
-    import oracle
+    if not args.no_extras:
+        out["extras"] = extras(torch, np, etics, workloads, stream)
+
     if not args.no_cpu_baseline:
+        import oracle
         # the oracle as it stands, all host threads, on the full workload: one force calculation
         t0 = time.perf_counter()
         rA, rB = oracle.scf_coeffs(p.x, p.y, p.z, p.m, nmax, lmax)
@@ -169,8 +272,8 @@ def main():
         cpu_s = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": n / cpu_s, "unit": "particles/s", "cores": oracle.num_threads(),
                                "kind": "oracle",
-                               "sample": f"the full workload (N={n}, ({nmax},{lmax})), one force calculation, "
-                                         f"{cpu_s:.2f} s"}
+                               "sample": f"the full workload (N={n}, ({nmax},{lmax})), one force calculation "
+                                         f"(coefficients then potential and acceleration), {cpu_s:.2f} s"}
         A, B, pot, ax, ay, az = res
         ce = accuracy.coeff_errors(A, B, rA, rB)
         fe = accuracy.summarize(accuracy.force_rel_err(ax, ay, az, rx, ry, rz))
@@ -183,6 +286,54 @@ def main():
                 "force": accuracy.summarize(accuracy.force_rel_err(ax, ay, az, rx, ry, rz)),
                 "pot": accuracy.summarize(accuracy.pot_rel_err(pot, rp))}
     print(json.dumps(out), flush=True)
+
+
+def extras(torch, np, etics, workloads, stream, reps=10):
+    """MEX force (N = 10^6, lmax = 10) and the batched hipGraph leapfrog step."""
+    ex = {}
+    p = workloads.make_config(4)
+    n = p.x.shape[0]
+    x, y, z, m = (torch.from_numpy(a).cuda() for a in (p.x, p.y, p.z, p.m))
+    for name, prec in (("mixed", etics.ETICS_MIXED_FP64ACC), ("fp64", etics.ETICS_FP64)):
+        pot, ax, ay, az = (torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(4))
+        ws = etics.workspace(etics.etics_mex_workspace_size(n, 10, prec), "cuda")
+        call = lambda: etics.etics_mex_force(x, y, z, m, 10, prec, etics.ETICS_POT_ACC, pot, ax, ay, az, ws,
+                                             stream)
+        call()
+        kt = KernelTimer(torch, etics, reps, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            kt.arm()
+            call()
+        e1.record(stream)
+        etics.etics_set_timing_events(None, None)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        ex[f"mex_{name}"] = {"workload": "mex_plummer_hernquist_n1e6_l10", "ms_per_call": ms,
+                             "particles_per_s": n / (ms * 1e-3), "synthesis_kernel_ms": kt.mean_ms()}
+    del x, y, z, m
+    q = workloads.make_config(5)
+    nt = q.x.shape[0]
+    st = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (q.x, q.y, q.z, q.vx, q.vy, q.vz, q.m)]
+    off = torch.from_numpy(q.offsets).cuda()
+    prec = etics.ETICS_MIXED_FP64ACC
+    ws = etics.workspace(etics.etics_batched_workspace_size(nt, 256, 8, 6, prec), "cuda")
+    etics.etics_leapfrog_scf_batched(*st, off, 8, 6, 0.01, 2, prec, 0, ws, stream)  # capture + warm
+    nsteps = 100
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    etics.etics_leapfrog_scf_batched(*st, off, 8, 6, 0.01, nsteps, prec, 0, ws, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    # one call = one extra force calculation at the start + nsteps graph replays
+    ex["leapfrog_batched_mixed"] = {"workload": "batched_256_spheres_n8_l6", "particles": nt, "nsteps": nsteps,
+                                    "ms_per_call": ms, "ms_per_step": ms / (nsteps + 1),
+                                    "particle_steps_per_s": nt * (nsteps + 1) / (ms * 1e-3)}
+    return ex
 
 
 if __name__ == "__main__":

@@ -158,6 +158,18 @@ int etics_leapfrog_scf_batched(double* x, double* y, double* z, double* vx, doub
                                int nmax, int lmax, int precision, double dt, int nsteps, int flags,
                                void* workspace, size_t ws_bytes, void* stream);
 
+/* Measurement support (no passage of the paper; used to time the kernels against
+   their roofline).  before/after are hipEvent_t handles created by the caller.  While
+   set, every later compute call of the calling thread records `before` on its stream
+   right before its main kernel and `after` right after it: the coefficient kernel
+   (etics_scf_coeffs, etics_scf_coeffs_batched; not the final fixed-order sum), the
+   force kernel (etics_scf_force, etics_scf_force_batched; not the coefficient
+   rescale before it) and the synthesis kernel of etics_mex_force (not the sort and
+   the ordered sums).  etics_leapfrog_scf_batched records nothing.  (NULL, NULL)
+   turns it off; exactly one NULL is ETICS_EINVAL.  The library does not own the
+   events and keeps only their handles. */
+int etics_set_timing_events(void* before, void* after);
+
 /* Message describing the last non-zero return on the calling thread ("" if none). */
 const char* etics_last_error(void);
 

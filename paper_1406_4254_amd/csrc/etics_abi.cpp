@@ -22,6 +22,20 @@ int hip_fail(hipError_t e, const char* where) {
   return ETICS_EHIP;
 }
 
+static thread_local TimingHook g_hook;
+
+TimingHook& timing_hook() { return g_hook; }
+
+int hook_before(hipStream_t st) {
+  if (!g_hook.before || g_hook.suspended) return ETICS_OK;
+  return hip_fail(hipEventRecord(g_hook.before, st), "hipEventRecord(timing before)");
+}
+
+int hook_after(hipStream_t st) {
+  if (!g_hook.after || g_hook.suspended) return ETICS_OK;
+  return hip_fail(hipEventRecord(g_hook.after, st), "hipEventRecord(timing after)");
+}
+
 static int einval(const char* what) {
   set_error(std::string("invalid argument: ") + what);
   return ETICS_EINVAL;
@@ -54,6 +68,14 @@ extern "C" {
 int etics_coeff_count(int nmax, int lmax) {
   if (!valid_cut(nmax, lmax)) return -1;
   return coeff_count(nmax, lmax);
+}
+
+int etics_set_timing_events(void* before, void* after) {
+  if ((before == nullptr) != (after == nullptr))
+    return einval("timing events must both be set or both be NULL");
+  g_hook.before = static_cast<hipEvent_t>(before);
+  g_hook.after = static_cast<hipEvent_t>(after);
+  return ETICS_OK;
 }
 
 const char* etics_last_error(void) { return g_last_error.c_str(); }

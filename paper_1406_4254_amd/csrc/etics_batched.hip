@@ -217,8 +217,8 @@ std::mutex g_graph_mutex;
 GraphCache g_graph;
 
 void drop_graph(GraphCache& g) {
-  if (g.exec) hipGraphExecDestroy(g.exec);
-  if (g.graph) hipGraphDestroy(g.graph);
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
   g.exec = nullptr;
   g.graph = nullptr;
   g.valid = false;
@@ -231,6 +231,12 @@ int run_leapfrog(double* x, double* y, double* z, double* vx, double* vy, double
                  int lmax, int prec, double dt, int nsteps, int flags, void* ws, size_t ws_bytes,
                  hipStream_t st) {
   LeapfrogCall c{x, y, z, vx, vy, vz, m, offsets, nsys, ntotal, nmax, lmax, prec, dt, ws, ws_bytes, 0};
+  // timing events are not recorded inside the steps (they would be captured too)
+  struct HookPause {
+    bool prev;
+    HookPause() : prev(timing_hook().suspended) { timing_hook().suspended = true; }
+    ~HookPause() { timing_hook().suspended = prev; }
+  } pause;
   int rc = hip_fail(hipGetDevice(&c.device), "hipGetDevice");
   if (rc) return rc;
   CoeffPlan plan;
@@ -265,7 +271,7 @@ int run_leapfrog(double* x, double* y, double* z, double* vx, double* vy, double
     hipGraph_t graph = nullptr;
     rc = hip_fail(hipStreamEndCapture(g_graph.capture, &graph), "hipStreamEndCapture");
     if (rs) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       return rs;
     }
     if (rc) return rc;

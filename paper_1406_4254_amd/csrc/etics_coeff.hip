@@ -141,6 +141,14 @@ __device__ __forceinline__ float2 merge(float2 a, float2 b) {  // double-float a
   return make_float2(hi, lo);
 }
 
+// two adjacent LDS values in one store (the address is 2-element aligned)
+__device__ __forceinline__ void store_pair(float* p, float a, float b) {
+  *reinterpret_cast<float2*>(p) = make_float2(a, b);
+}
+__device__ __forceinline__ void store_pair(double* p, double a, double b) {
+  *reinterpret_cast<double2*>(p) = make_double2(a, b);
+}
+
 // decode register block b of a cutoff (lmax, nchunks) into (l, n0, s0)
 template <int NB, int BS>
 __device__ __forceinline__ void decode_block(int b, int lmax, int nchunks, int& bl, int& n0,
@@ -256,18 +264,23 @@ struct CoeffWG {
         }
       }
       if (wave == kJP.ownerZ[m] && m <= lmax) {
-        constexpr int sc = m == 0 ? 0 : 2 * m - 1;
         T P2 = T(0), P1 = Pd;
-        Zp[zoff(m, BS) + sc] = P1 * cmc;
-        if constexpr (m > 0) Zp[zoff(m, BS) + sc + 1] = P1 * smc;
+        auto put = [&](auto lc2, T P) {
+          constexpr int l = decltype(lc2)::value;
+          if constexpr (m == 0) {
+            Zp[zoff(l, BS) + 2 * l] = P;
+          } else {  // (cos, sin) pair at an even slot of an 8-byte aligned row
+            store_pair(Zp + zoff(l, BS) + 2 * m - 2, P * cmc, P * smc);
+          }
+        };
+        put(std::integral_constant<int, m>{}, P1);
         static_for<LB - m>([&](auto kc) {
           constexpr int l = m + 1 + decltype(kc)::value;
           if (l <= lmax) {
             const T P = (T(kTab.c1[l][m]) * ctu) * P1 - (T(kTab.c2[l][m]) * tu2) * P2;
             P2 = P1;
             P1 = P;
-            Zp[zoff(l, BS) + sc] = P * cmc;
-            if constexpr (m > 0) Zp[zoff(l, BS) + sc + 1] = P * smc;
+            put(std::integral_constant<int, l>{}, P);
           }
         });
       }
@@ -327,8 +340,19 @@ struct CoeffWG {
           gv[buf][2 * q + 1] = f.y;
         }
       }
+      static_assert(BS % 2 == 0, "angular blocks are read in aligned pairs");
 #pragma unroll
-      for (int j = 0; j < BS; ++j) zv[buf][j] = zz[j];
+      for (int j = 0; j < BS; j += 2) {
+        if constexpr (sizeof(T) == 4) {
+          const float2 f = reinterpret_cast<const float2*>(zz)[j / 2];
+          zv[buf][j] = f.x;
+          zv[buf][j + 1] = f.y;
+        } else {
+          const double2 f = reinterpret_cast<const double2*>(zz)[j / 2];
+          zv[buf][j] = f.x;
+          zv[buf][j + 1] = f.y;
+        }
+      }
     };
     auto madd = [&](int buf) {
 #pragma unroll
@@ -336,13 +360,17 @@ struct CoeffWG {
 #pragma unroll
         for (int j = 0; j < BS; ++j) acc[i][j] = fma_(gv[buf][i], zv[buf][j], acc[i][j]);
     };
-    // two particles per trip, each one's LDS reads issued before the other's FMAs
+    // two particles per trip, each one's LDS reads issued before the other's FMAs.  The
+    // look-ahead read past the tile is clamped to its last particle (read, never used),
+    // so the reads need no branch and the two buffers keep their registers.
+    const int last = tp - 1;
     int p = my_stream;
-    if (p < tp) fetch(p, 0);
+    fetch(p < last ? p : last, 0);
     for (; p + streams < tp; p += 2 * streams) {
       fetch(p + streams, 1);
       madd(0);
-      if (p + 2 * streams < tp) fetch(p + 2 * streams, 0);
+      const int q = p + 2 * streams;
+      fetch(q < last ? q : last, 0);
       madd(1);
     }
     if (p < tp) madd(0);
@@ -375,8 +403,8 @@ struct CoeffWG {
       const int nn = nb0 + i;
       const int slot = sb0 + j;
       if (nn > nmax || slot > 2 * l) continue;
-      const int m = (slot + 1) / 2;
-      const bool is_sin = slot > 0 && (slot & 1) == 0;
+      const int m = slot == 2 * l ? 0 : slot / 2 + 1;
+      const bool is_sin = slot < 2 * l && (slot & 1) == 1;
       const int k = nn * L2 + l * (l + 1) / 2 + m;
       part[(is_sin ? K : 0) + k] = out[e];
     }
@@ -577,13 +605,16 @@ int launch_coeff_t(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) 
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(scf_coeff)");
     attr_set = true;
   }
+  int rc = hook_before(st);
+  if (rc) return rc;
   if constexpr (BATCHED)
     hipLaunchKernelGGL((scf_coeff_batched_kernel<T, LB, NB, BS, MODE>), dim3(grid), dim3(kCoeffThreads),
                        p.lds_bytes, st, a);
   else
     hipLaunchKernelGGL((scf_coeff_kernel<T, LB, NB, BS, MODE>), dim3(grid), dim3(kCoeffThreads),
                        p.lds_bytes, st, a);
-  return hip_fail(hipGetLastError(), "scf_coeff_kernel launch");
+  rc = hip_fail(hipGetLastError(), "scf_coeff_kernel launch");
+  return rc ? rc : hook_after(st);
 }
 
 template <bool BATCHED, typename T, int MODE, int LB, typename Args>

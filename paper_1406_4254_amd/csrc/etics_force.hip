@@ -314,11 +314,15 @@ int launch_force_any(const ForceArgs& a, int prec, int outputs, int grid, const 
                      hipStream_t st) {
   const int lb = a.lmax <= 2 ? 2 : (a.lmax + 1) / 2 * 2;
   const bool acc = (outputs & ETICS_ACC) != 0;
+  int rc = hook_before(st);
+  if (rc) return rc;
   if (prec == ETICS_FP64)
-    return acc ? launch_force_lb<double, true>(lb, a, grid, bi, st)
-               : launch_force_lb<double, false>(lb, a, grid, bi, st);
-  return acc ? launch_force_lb<float, true>(lb, a, grid, bi, st)
+    rc = acc ? launch_force_lb<double, true>(lb, a, grid, bi, st)
+             : launch_force_lb<double, false>(lb, a, grid, bi, st);
+  else
+    rc = acc ? launch_force_lb<float, true>(lb, a, grid, bi, st)
              : launch_force_lb<float, false>(lb, a, grid, bi, st);
+  return rc ? rc : hook_after(st);
 }
 
 ForceArgs make_force_args(const double* x, const double* y, const double* z, int64_t n, int nmax,

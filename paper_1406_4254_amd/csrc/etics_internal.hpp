@@ -15,6 +15,16 @@ namespace etics {
 void set_error(const std::string& msg);
 int hip_fail(hipError_t e, const char* where);
 
+// Timing events of the calling thread (etics_set_timing_events): recorded on the
+// stream right before and right after the main kernel of a compute call.
+struct TimingHook {
+  hipEvent_t before = nullptr, after = nullptr;
+  bool suspended = false;  // set while a call replays captured work (leapfrog)
+};
+TimingHook& timing_hook();
+int hook_before(hipStream_t st);
+int hook_after(hipStream_t st);
+
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 inline int lm_count(int lmax) { return (lmax + 1) * (lmax + 2) / 2; }
 inline int coeff_count(int nmax, int lmax) { return (nmax + 1) * lm_count(lmax); }

@@ -508,8 +508,11 @@ int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
   hipLaunchKernelGGL((mex_tile_scan_kernel<LB>), dim3((ncol + 255) / 256), dim3(256), 0, st, a);
   rc = hip_fail(hipGetLastError(), "mex_tile_scan_kernel launch");
   if (rc) return rc;
+  rc = hook_before(st);
+  if (rc) return rc;
   hipLaunchKernelGGL((mex_force_kernel<T, LB>), dim3(ntiles), dim3(kMexTile), lds, st, a);
-  return hip_fail(hipGetLastError(), "mex_force_kernel launch");
+  rc = hip_fail(hipGetLastError(), "mex_force_kernel launch");
+  return rc ? rc : hook_after(st);
 }
 
 template <typename T>

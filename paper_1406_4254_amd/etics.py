@@ -35,7 +35,7 @@ EXPORTED = [
     "etics_coeff_count", "etics_scf_workspace_size", "etics_scf_coeffs", "etics_scf_force",
     "etics_mex_workspace_size", "etics_mex_force", "etics_batched_workspace_size",
     "etics_scf_coeffs_batched", "etics_scf_force_batched", "etics_leapfrog_scf_batched",
-    "etics_last_error", "etics_version",
+    "etics_set_timing_events", "etics_last_error", "etics_version",
 ]
 
 
@@ -85,6 +85,8 @@ def lib():
                                                  _int, _int, _int, ctypes.c_double, _int, _int, _vp, _sz,
                                                  _vp]
         L.etics_leapfrog_scf_batched.restype = _int
+        L.etics_set_timing_events.argtypes = [_vp, _vp]
+        L.etics_set_timing_events.restype = _int
         L.etics_last_error.restype = ctypes.c_char_p
         L.etics_version.restype = ctypes.c_char_p
         _lib = L
@@ -124,6 +126,19 @@ def workspace(nbytes: int, device) -> torch.Tensor:
 
 def etics_version() -> str:
     return lib().etics_version().decode()
+
+
+def etics_set_timing_events(before, after) -> None:
+    """Record two torch.cuda.Event objects around the main kernel of every later
+    compute call of this thread (None, None: stop).  The events must already exist on
+    the device (record each once before passing it)."""
+    if (before is None) != (after is None):
+        raise ValueError("pass both events or neither")
+    hb = None if before is None else ctypes.c_void_p(before.cuda_event)
+    ha = None if after is None else ctypes.c_void_p(after.cuda_event)
+    if before is not None and not (before.cuda_event and after.cuda_event):
+        raise ValueError("record the events once before passing them")
+    _check(lib().etics_set_timing_events(hb, ha))
 
 
 def etics_coeff_count(nmax: int, lmax: int) -> int:

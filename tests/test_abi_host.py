@@ -98,3 +98,13 @@ def test_invalid_arguments_rejected_without_device_work(L):
 def test_version(L):
     L.etics_version.restype = ctypes.c_char_p
     assert b"gfx950" in L.etics_version()
+
+
+def test_timing_events_need_both_or_neither(L):
+    t = L.etics_set_timing_events
+    t.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    L.etics_last_error.restype = ctypes.c_char_p
+    assert t(ctypes.c_void_p(0x1000), None) == -1
+    assert b"timing" in L.etics_last_error()
+    assert t(None, ctypes.c_void_p(0x1000)) == -1
+    assert t(None, None) == 0  # off: stores nothing, touches no device
