@@ -420,23 +420,27 @@ __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coe
   w.zero_slots();
   __syncthreads();
 
+  // each workgroup takes a contiguous run of tiles, so the cache lines shared by two
+  // neighbouring tiles are fetched once, into one L2
+  const int t0 = int(int64_t(blockIdx.x) * a.ntiles / gridDim.x);
+  const int t1 = int(int64_t(blockIdx.x + 1) * a.ntiles / gridDim.x);
   // particle data of the first tile (later tiles are prefetched during phase 2)
   double xd = 0.0, yd = 0.0, zd = 0.0, md = 0.0;
   auto load_particle = [&](int tile) {
     const int64_t pi = int64_t(tile) * a.tp + w.lane;
-    const bool valid = tile < a.ntiles && w.lane < a.tp && pi < a.n;
+    const bool valid = tile < t1 && w.lane < a.tp && pi < a.n;
     xd = valid ? a.x[pi] : 0.0;
     yd = valid ? a.y[pi] : 0.0;
     zd = valid ? a.z[pi] : 0.0;
     md = valid ? a.m[pi] : 0.0;
   };
-  load_particle(blockIdx.x);
+  load_particle(t0);
 
   int tcount = 0;
-  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+  for (int tile = t0; tile < t1; ++tile) {
     w.phase1(xd, yd, zd, md);
     __syncthreads();
-    load_particle(tile + gridDim.x);  // next tile's particles load while phase 2 runs
+    load_particle(tile + 1);  // next tile's particles load while phase 2 runs
     w.phase2();
     if (++tcount == a.flush_tiles) {
       tcount = 0;

@@ -34,7 +34,7 @@ inline int coeff_count(int nmax, int lmax) { return (nmax + 1) * lm_count(lmax);
 constexpr int kCoeffThreads = 256;  // 4 wavefronts
 constexpr int kMaxJobs = 32;        // basis jobs per wavefront (2 (lmax+1) <= 30)
 constexpr int kMaxStreams = 32;
-constexpr int kUnitParticles = 1024;  // batched work unit: particles of one system
+constexpr int kUnitParticles = 4096;  // batched work unit: particles of one system
 
 struct CoeffPlan {
   int nmax, lmax, prec;   // prec: ETICS_* precision mode

@@ -14,14 +14,18 @@
 //   1. mex_keys: FP64 key (x*x + y*y) + z*z, each operation rounded, as its IEEE bit
 //      pattern (order-preserving for non-negative values), with the particle index.
 //   2. LSD radix sort of (key, index), 8 bits per pass: per-block digit histograms,
-//      one exclusive scan of the histograms, a stable scatter whose in-block ranks come
-//      from wavefront ballots.  Stable, so equal keys stay in index order.
+//      a per-digit exclusive scan over blocks (one workgroup per digit), a stable
+//      scatter whose in-block ranks come from wavefront ballots.  Stable, so equal keys
+//      stay in index order.
 //   3. mex_tile_sums: per tile of sorted particles, the sums of the inward and outward
 //      summands (FP64).
-//   4. mex_tile_scan: exclusive prefix (inward) and suffix (outward) over tiles.
-//   5. mex_force: per tile, the summands again, exclusive scans inside the tile in LDS,
-//      plus the tile offsets, give q and p of every particle; then the synthesis and
-//      the Cartesian force, scattered back to the caller's order.
+//   4. tile offsets: exclusive prefix (inward) and suffix (outward) over tiles, in
+//      three parallel steps (sums of blocks of tiles, a scan over the blocks, then the
+//      tiles of every block).
+//   5. mex_force: per tile, the summands again, exclusive scans inside the tile (each
+//      column staged in LDS, scanned by one wavefront with shuffles), plus the tile
+//      offsets, give q and p of every particle; then the synthesis and the Cartesian
+//      force, scattered back to the caller's order.
 // Radial powers, moments, scans and synthesis accumulations are FP64 in every mode;
 // the MIXED modes evaluate Ybar_lm, its derivatives and (cos, sin)(m phi) in FP32.
 #include <hip/hip_runtime.h>
@@ -34,9 +38,36 @@
 
 namespace etics {
 
-constexpr int kMexTile = 256;       // sorted particles per tile (one per thread)
+constexpr int kMexTile = 128;       // sorted particles per tile (one per thread, 2 wavefronts)
+constexpr int kMexBlockTiles = 64;  // tiles per block of the tile-offset scan
 constexpr int kSortSeg = 4096;      // keys per radix block
 constexpr int kSortThreads = 256;
+
+// ------------------------------------------------------------------ block scans
+// exclusive prefix sum of one value per thread over a workgroup of 256 threads
+// (4 wavefronts); `wsum` is 4 words of LDS.  Returns the exclusive prefix; *total gets
+// the workgroup sum.
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t s = wsum[q];
+    before += q < w ? s : 0u;
+    all += s;
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
 
 // ------------------------------------------------------------------ keys
 __global__ __launch_bounds__(256) void mex_keys_kernel(const double* __restrict__ x,
@@ -70,29 +101,33 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint64_t
   hist[size_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan of hist (256 * nblk entries, digit-major) in one workgroup
-__global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__ hist, int total) {
-  __shared__ uint32_t part[1024];
+// hist[d * nblk + b] -> exclusive prefix over blocks b of digit d (in place);
+// totals[d] = keys with digit d.  One workgroup per digit.
+__global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restrict__ hist, int nblk,
+                                                               uint32_t* __restrict__ totals) {
+  __shared__ uint32_t wsum[4];
+  uint32_t* row = hist + size_t(blockIdx.x) * nblk;
   const int t = threadIdx.x;
-  const int per = (total + 1023) / 1024;
-  const int a = t * per, b = (a + per < total) ? a + per : total;
-  uint32_t s = 0;
-  for (int i = a; i < b; ++i) s += hist[i];
-  part[t] = s;
-  __syncthreads();
-  // exclusive scan of the 1024 partial sums (Hillis-Steele on inclusive, then shift)
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t v = t >= off ? part[t - off] : 0u;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  uint32_t carry = 0;
+  for (int base = 0; base < nblk; base += 4 * 256) {
+    uint32_t v[4], s = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = base + 4 * t + j;
+      v[j] = i < nblk ? row[i] : 0u;
+      s += v[j];
+    }
+    uint32_t chunk;
+    uint32_t run = carry + block_excl_scan_u32(s, wsum, &chunk);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = base + 4 * t + j;
+      if (i < nblk) row[i] = run;
+      run += v[j];
+    }
+    carry += chunk;
   }
-  uint32_t run = t > 0 ? part[t - 1] : 0u;
-  for (int i = a; i < b; ++i) {
-    const uint32_t v = hist[i];
-    hist[i] = run;
-    run += v;
-  }
+  if (t == 0) totals[blockIdx.x] = carry;
 }
 
 // Stable scatter.  The block walks its segment in chunks of 256 keys (one per
@@ -101,11 +136,15 @@ __global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__
 // wavefront, from 8 ballots).
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, int64_t n, int shift, int nblk, const uint32_t* __restrict__ hist) {
+    uint32_t* __restrict__ vout, int64_t n, int shift, int nblk, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ totals) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t wsum[4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  base[t] = hist[size_t(t) * nblk + blockIdx.x];
+  uint32_t all;
+  const uint32_t digit_start = block_excl_scan_u32(totals[t], wsum, &all);
+  base[t] = digit_start + hist[size_t(t) * nblk + blockIdx.x];
   const int64_t b0 = int64_t(blockIdx.x) * kSortSeg;
   const int64_t b1 = b0 + kSortSeg < n ? b0 + kSortSeg : n;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -174,35 +213,64 @@ struct MexArgs {
   const uint32_t* perm;      // sorted position -> particle index
   double* tsum;              // [ntiles][2][(LB+1)^2]  tile sums: inward, outward
   double* toff;              // [ntiles][2][(LB+1)^2]  exclusive tile prefix / suffix
+  double* bsum;              // [nblocks][2][(LB+1)^2] sums of blocks of tiles, then their
+                             //                        exclusive prefix / suffix
   double *pot, *ax, *ay, *az;
-  int lmax, ntiles, want_pot, want_acc;
+  int lmax, ntiles, nblocks, want_pot, want_acc;
 };
 
 constexpr int mex_nc(int lb) { return (lb + 1) * (lb + 1); }
 constexpr int mex_coff(int l) { return l * l; }  // first component of l (2l+1 per l)
 
 // Per l: each thread writes its 2(2l+1) summands to LDS, then every column is summed
-// (tile sums) or scanned (force).  Column c of the LDS block is component c with rows
-// = threads (sorted order).
-template <typename T, int LB, int l>
-__device__ __forceinline__ void mex_summands_row(const MexParticle<T>& p, const T (&Y)[LB + 2][LB + 2],
+// (tile sums) or scanned (force).  The LDS block is column-major: component c of the
+// particle in row (sorted position within the tile) t is at col0[c * CS], col0 = S + t.
+template <typename T, int LB, int l, int CS>
+__device__ __forceinline__ void mex_summands_col(const MexParticle<T>& p, const T (&Y)[LB + 2][LB + 2],
                                                  const T* cm, const T* sm, double rl, double rm,
-                                                 double* row) {
-  // row[0 .. 2l]: inward (m r^l Ybar trig), row[2l+1 .. 4l+1]: outward (m r^-(l+1) Ybar trig)
-  const double wi = p.mass * rl;
-  const double wo = p.at_origin ? 0.0 : p.mass * rm;
+                                                 bool valid, double* col0) {
+  // components 0 .. 2l: inward (m r^l Ybar trig); 2l+1 .. 4l+1: outward (m r^-(l+1) Ybar trig)
+  const double wi = valid ? p.mass * rl : 0.0;
+  const double wo = (valid && !p.at_origin) ? p.mass * rm : 0.0;
   static_for<l + 1>([&](auto mc) {
     constexpr int m = decltype(mc)::value;
     constexpr int sc = m == 0 ? 0 : 2 * m - 1;
     const double yc = double(Y[l][m] * cm[m]);
-    row[sc] = wi * yc;
-    row[2 * l + 1 + sc] = wo * yc;
+    col0[sc * CS] = wi * yc;
+    col0[(2 * l + 1 + sc) * CS] = wo * yc;
     if constexpr (m > 0) {
       const double ys = double(Y[l][m] * sm[m]);
-      row[sc + 1] = wi * ys;
-      row[2 * l + 1 + sc + 1] = wo * ys;
+      col0[(sc + 1) * CS] = wi * ys;
+      col0[(2 * l + 1 + sc + 1) * CS] = wo * ys;
     }
   });
+}
+
+// wavefront-wide sums of one FP64 value per lane, in a fixed shuffle tree
+__device__ __forceinline__ double wave_excl_prefix(double x, int lane) {
+  double incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  const double ex = __shfl_up(incl, 1);
+  return lane == 0 ? 0.0 : ex;
+}
+__device__ __forceinline__ double wave_excl_suffix(double x, int lane) {
+  double incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_down(incl, o);
+    if (lane + o < 64) incl += y;
+  }
+  const double ex = __shfl_down(incl, 1);
+  return lane == 63 ? 0.0 : ex;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+  return x;
 }
 
 template <typename T, int LB, int r>
@@ -215,94 +283,119 @@ __device__ __forceinline__ void mex_legendre_row(T (&Y)[LB + 2][LB + 2], T ct, T
   });
 }
 
+// per-particle set-up shared by the tile-sum and force kernels
+template <typename T, int LB>
+struct MexLane {
+  MexParticle<T> p;
+  T cm[LB + 1], sm[LB + 1];
+  T Y[LB + 2][LB + 2];
+  uint32_t pidx;
+  bool valid;
+
+  __device__ __forceinline__ void load(const MexArgs<LB>& a, int64_t k) {
+    valid = k < a.n;
+    pidx = 0;
+    double px = 0, py = 0, pz = 0, pm = 0;
+    if (valid) {
+      pidx = a.perm[k];
+      px = a.x[pidx];
+      py = a.y[pidx];
+      pz = a.z[pidx];
+      pm = a.m[pidx];
+    }
+    p = mex_particle<T>(px, py, pz, pm);
+    cm[0] = T(1);
+    sm[0] = T(0);
+#pragma unroll
+    for (int m = 1; m <= LB; ++m) {
+      cm[m] = cm[m - 1] * p.cp - sm[m - 1] * p.sp;
+      sm[m] = sm[m - 1] * p.cp + cm[m - 1] * p.sp;
+    }
+    Y[0][0] = T(kTab.c1[0][0]);
+  }
+};
+
 // tile sums of inward / outward summands
 template <typename T, int LB>
 __global__ __launch_bounds__(kMexTile) void mex_tile_sums_kernel(const MexArgs<LB> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* S = reinterpret_cast<double*>(lds_raw);  // [kMexTile][4l+2 (+1)]
+  double* S = reinterpret_cast<double*>(lds_raw);  // [2(2l+1)][kMexTile]
   constexpr int NC = mex_nc(LB);
-  const int t = threadIdx.x;
-  const int64_t k = int64_t(blockIdx.x) * kMexTile + t;
-  const bool valid = k < a.n;
-  double px = 0, py = 0, pz = 0, pm = 0;
-  if (valid) {
-    const uint32_t i = a.perm[k];
-    px = a.x[i];
-    py = a.y[i];
-    pz = a.z[i];
-    pm = a.m[i];
-  }
-  const MexParticle<T> p = mex_particle<T>(px, py, pz, pm);
-  T cm[LB + 1], sm[LB + 1];
-  cm[0] = T(1);
-  sm[0] = T(0);
-#pragma unroll
-  for (int m = 1; m <= LB; ++m) {
-    cm[m] = cm[m - 1] * p.cp - sm[m - 1] * p.sp;
-    sm[m] = sm[m - 1] * p.cp + cm[m - 1] * p.sp;
-  }
-  T Y[LB + 2][LB + 2];
-  Y[0][0] = T(kTab.c1[0][0]);
-  double rl = 1.0, rm = p.rinv;  // r^l, r^-(l+1)
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  MexLane<T, LB> q;
+  q.load(a, int64_t(blockIdx.x) * kMexTile + t);
+  double rl = 1.0, rm = q.p.rinv;  // r^l, r^-(l+1)
   double* out = a.tsum + size_t(blockIdx.x) * 2 * NC;
   static_for<LB + 1>([&](auto lc) {
     constexpr int l = decltype(lc)::value;
     if (l > a.lmax) return;
-    if constexpr (l >= 1) mex_legendre_row<T, LB, l>(Y, p.ct, p.st);
-    constexpr int W = 2 * (2 * l + 1);
-    constexpr int RS = W | 1;  // odd row stride (doubles)
-    double* row = S + t * RS;
-    if (valid) {
-      mex_summands_row<T, LB, l>(p, Y, cm, sm, rl, rm, row);
-    } else {
-#pragma unroll
-      for (int c = 0; c < W; ++c) row[c] = 0.0;
+    if constexpr (l >= 1) mex_legendre_row<T, LB, l>(q.Y, q.p.ct, q.p.st);
+    constexpr int W = 2 * (2 * l + 1), H = 2 * l + 1;
+    mex_summands_col<T, LB, l, kMexTile>(q.p, q.Y, q.cm, q.sm, rl, rm, q.valid, S + t);
+    __syncthreads();
+    // one wavefront per column: two rows per lane, then a shuffle tree
+    for (int c = wave; c < W; c += kMexTile / 64) {
+      const double2 v = *reinterpret_cast<const double2*>(S + c * kMexTile + 2 * lane);
+      const double tot = wave_sum(v.x + v.y);
+      if (lane == 0) out[(c < H ? 0 : NC) + mex_coff(l) + (c < H ? c : c - H)] = tot;
     }
     __syncthreads();
-    // column sums: 4 threads per column, each over 64 rows in order, then in order
-    constexpr int Q = 4;
-    double part = 0.0;
-    const int col = t / Q, seg = t % Q;
-    if (col < W) {
-      for (int rr = seg * (kMexTile / Q); rr < (seg + 1) * (kMexTile / Q); ++rr) part += S[rr * RS + col];
-    }
-    __syncthreads();
-    if (col < W) S[seg * RS + col] = part;  // rows 0..Q-1 reused for the partials
-    __syncthreads();
-    if (t < W) {
-      double s = 0.0;
-      for (int q = 0; q < Q; ++q) s += S[q * RS + t];
-      const int side = t < 2 * l + 1 ? 0 : 1;
-      const int c = side == 0 ? t : t - (2 * l + 1);
-      out[side * NC + mex_coff(l) + c] = s;
-    }
-    __syncthreads();
-    rl *= p.r;
-    rm *= p.rinv;
+    rl *= q.p.r;
+    rm *= q.p.rinv;
   });
 }
 
-// exclusive prefix (inward side) and suffix (outward side) over tiles; one thread per
-// component column, serial in tile order
+// tile offsets, step 1: sums of blocks of kMexBlockTiles tiles (one workgroup per block)
 template <int LB>
-__global__ __launch_bounds__(256) void mex_tile_scan_kernel(const MexArgs<LB> a) {
+__global__ __launch_bounds__(256) void mex_block_sums_kernel(const MexArgs<LB> a) {
   constexpr int NC = mex_nc(LB);
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nc = (a.lmax + 1) * (a.lmax + 1);
-  if (c >= 2 * nc) return;
-  const int side = c < nc ? 0 : 1;
-  const int comp = side == 0 ? c : c - nc;
-  double run = 0.0;
-  if (side == 0) {
-    for (int tl = 0; tl < a.ntiles; ++tl) {
-      const size_t o = (size_t(tl) * 2 + 0) * NC + comp;
-      const double v = a.tsum[o];
-      a.toff[o] = run;
+  const int ncu = (a.lmax + 1) * (a.lmax + 1);
+  const int b = blockIdx.x;
+  const int t0 = b * kMexBlockTiles;
+  const int t1 = t0 + kMexBlockTiles < a.ntiles ? t0 + kMexBlockTiles : a.ntiles;
+  for (int c = threadIdx.x; c < 2 * ncu; c += blockDim.x) {
+    const int side = c < ncu ? 0 : 1;
+    const int comp = side == 0 ? c : c - ncu;
+    double s = 0.0;
+    for (int tl = t0; tl < t1; ++tl) s += a.tsum[(size_t(tl) * 2 + side) * NC + comp];
+    a.bsum[(size_t(b) * 2 + side) * NC + comp] = s;
+  }
+}
+
+// step 2: exclusive prefix (inward) / suffix (outward) over the blocks, in place
+template <int LB>
+__global__ __launch_bounds__(256) void mex_block_scan_kernel(const MexArgs<LB> a) {
+  constexpr int NC = mex_nc(LB);
+  const int ncu = (a.lmax + 1) * (a.lmax + 1);
+  for (int c = threadIdx.x; c < 2 * ncu; c += blockDim.x) {
+    const int side = c < ncu ? 0 : 1;
+    const int comp = side == 0 ? c : c - ncu;
+    double run = 0.0;
+    for (int k = 0; k < a.nblocks; ++k) {
+      const int b = side == 0 ? k : a.nblocks - 1 - k;
+      double* e = a.bsum + (size_t(b) * 2 + side) * NC + comp;
+      const double v = *e;
+      *e = run;
       run += v;
     }
-  } else {
-    for (int tl = a.ntiles - 1; tl >= 0; --tl) {
-      const size_t o = (size_t(tl) * 2 + 1) * NC + comp;
+  }
+}
+
+// step 3: the tiles of every block, starting from the block's offset
+template <int LB>
+__global__ __launch_bounds__(256) void mex_tile_offsets_kernel(const MexArgs<LB> a) {
+  constexpr int NC = mex_nc(LB);
+  const int ncu = (a.lmax + 1) * (a.lmax + 1);
+  const int b = blockIdx.x;
+  const int t0 = b * kMexBlockTiles;
+  const int t1 = t0 + kMexBlockTiles < a.ntiles ? t0 + kMexBlockTiles : a.ntiles;
+  for (int c = threadIdx.x; c < 2 * ncu; c += blockDim.x) {
+    const int side = c < ncu ? 0 : 1;
+    const int comp = side == 0 ? c : c - ncu;
+    double run = a.bsum[(size_t(b) * 2 + side) * NC + comp];
+    for (int k = t0; k < t1; ++k) {
+      const int tl = side == 0 ? k : t1 - 1 - (k - t0);
+      const size_t o = (size_t(tl) * 2 + side) * NC + comp;
       const double v = a.tsum[o];
       a.toff[o] = run;
       run += v;
@@ -314,33 +407,13 @@ __global__ __launch_bounds__(256) void mex_tile_scan_kernel(const MexArgs<LB> a)
 template <typename T, int LB>
 __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* S = reinterpret_cast<double*>(lds_raw);
-  __shared__ double segtot[4][64];
+  double* S = reinterpret_cast<double*>(lds_raw);  // [2(2l+1)][kMexTile]
   constexpr int NC = mex_nc(LB);
-  const int t = threadIdx.x;
-  const int64_t k = int64_t(blockIdx.x) * kMexTile + t;
-  const bool valid = k < a.n;
-  uint32_t pidx = 0;
-  double px = 0, py = 0, pz = 0, pm = 0;
-  if (valid) {
-    pidx = a.perm[k];
-    px = a.x[pidx];
-    py = a.y[pidx];
-    pz = a.z[pidx];
-    pm = a.m[pidx];
-  }
-  const MexParticle<T> p = mex_particle<T>(px, py, pz, pm);
-  T cm[LB + 1], sm[LB + 1];
-  cm[0] = T(1);
-  sm[0] = T(0);
-#pragma unroll
-  for (int m = 1; m <= LB; ++m) {
-    cm[m] = cm[m - 1] * p.cp - sm[m - 1] * p.sp;
-    sm[m] = sm[m - 1] * p.cp + cm[m - 1] * p.sp;
-  }
-  T Y[LB + 2][LB + 2];
-  Y[0][0] = T(kTab.c1[0][0]);
-  mex_legendre_row<T, LB, 1>(Y, p.ct, p.st);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  MexLane<T, LB> q;
+  q.load(a, int64_t(blockIdx.x) * kMexTile + t);
+  const MexParticle<T>& p = q.p;
+  mex_legendre_row<T, LB, 1>(q.Y, p.ct, p.st);
   double rl = 1.0, rm = p.rinv;                      // r^l, r^-(l+1)
   double rlm1 = 0.0;                                 // r^(l-1)  (0 for l = 0)
   double Phi = 0.0, ar = 0.0, at = 0.0, ap = 0.0;
@@ -349,63 +422,44 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
     constexpr int l = decltype(lc)::value;
     if (l > a.lmax) return;
     // Legendre row l+1 (for m Ybar / sin)
-    mex_legendre_row<T, LB, l + 1>(Y, p.ct, p.st);
-    constexpr int W = 2 * (2 * l + 1);
-    constexpr int RS = W | 1;
-    double* row = S + t * RS;
-    if (valid) {
-      mex_summands_row<T, LB, l>(p, Y, cm, sm, rl, rm, row);
-    } else {
-#pragma unroll
-      for (int c = 0; c < W; ++c) row[c] = 0.0;
-    }
+    mex_legendre_row<T, LB, l + 1>(q.Y, p.ct, p.st);
+    constexpr int W = 2 * (2 * l + 1), H = 2 * l + 1;
+    mex_summands_col<T, LB, l, kMexTile>(p, q.Y, q.cm, q.sm, rl, rm, q.valid, S + t);
     __syncthreads();
-    // exclusive scans of every column inside the tile: 4 segments of 64 rows per
-    // column; inward columns run forward, outward columns backward
-    constexpr int Q = 4, SEGL = kMexTile / Q;
-    const int col = t / Q, seg = t % Q;
-    const bool fwd = col < 2 * l + 1;
-    if (col < W) {
-      double run = 0.0;
+    // exclusive scans of every column inside the tile, one wavefront per column (two
+    // rows per lane, then a shuffle tree across lanes); inward columns run forward,
+    // outward columns backward; the tile's offset from the other tiles is added
+    for (int c = wave; c < W; c += kMexTile / 64) {
+      const bool fwd = c < H;
+      double* cp = S + c * kMexTile + 2 * lane;
+      const double2 v = *reinterpret_cast<const double2*>(cp);
+      const double off = offs[(fwd ? 0 : NC) + mex_coff(l) + (fwd ? c : c - H)];
+      double e0, e1, before;
       if (fwd) {
-        for (int rr = seg * SEGL; rr < (seg + 1) * SEGL; ++rr) {
-          const double v = S[rr * RS + col];
-          S[rr * RS + col] = run;
-          run += v;
-        }
+        e0 = 0.0;
+        e1 = v.x;
+        before = wave_excl_prefix(v.x + v.y, lane);
       } else {
-        for (int rr = (seg + 1) * SEGL - 1; rr >= seg * SEGL; --rr) {
-          const double v = S[rr * RS + col];
-          S[rr * RS + col] = run;
-          run += v;
-        }
+        e1 = 0.0;
+        e0 = v.y;
+        before = wave_excl_suffix(v.y + v.x, lane);
       }
-      segtot[seg][col] = run;
+      const double base = off + before;
+      *reinterpret_cast<double2*>(cp) = make_double2(base + e0, base + e1);
     }
     __syncthreads();
-    if (col < W) {
-      const int side = fwd ? 0 : 1;
-      const int c = fwd ? col : col - (2 * l + 1);
-      double off = offs[side * NC + mex_coff(l) + c];
-      if (fwd) {
-        for (int q = 0; q < seg; ++q) off += segtot[q][col];
-      } else {
-        for (int q = Q - 1; q > seg; --q) off += segtot[q][col];
-      }
-      for (int rr = seg * SEGL; rr < (seg + 1) * SEGL; ++rr) S[rr * RS + col] += off;
-    }
-    __syncthreads();
-    // synthesis of this l from the particle's own q (row[0..2l]) and p (row[2l+1..])
+    // synthesis of this l from the particle's own q (components 0..2l) and p (2l+1..)
     {
+      const double* row = S + t;
       const double g = 4.0 * kPi / (2.0 * l + 1.0);
       static_for<l + 1>([&](auto mc) {
         constexpr int m = decltype(mc)::value;
         constexpr int sc = m == 0 ? 0 : 2 * m - 1;
         const double w = (m == 0 ? 1.0 : 2.0) * g;
-        const double qc = row[sc], pc = row[2 * l + 1 + sc];
-        const double qs = m > 0 ? row[sc + 1] : 0.0;
-        const double ps = m > 0 ? row[2 * l + 1 + sc + 1] : 0.0;
-        const double c = double(cm[m]), s = double(sm[m]);
+        const double qc = row[sc * kMexTile], pc = row[(H + sc) * kMexTile];
+        const double qs = m > 0 ? row[(sc + 1) * kMexTile] : 0.0;
+        const double ps = m > 0 ? row[(H + sc + 1) * kMexTile] : 0.0;
+        const double c = double(q.cm[m]), s = double(q.sm[m]);
         // radial factors: inward q r^-(l+1), outward p r^l; the inward part is absent
         // for a particle at the origin
         const double fq = p.at_origin ? 0.0 : rm;
@@ -418,21 +472,21 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
                                       : (qc * c + qs * s) * rm * p.rinv + (pc * c + ps * s) * rlm1;
         const double f = p.at_origin ? (ps * c - pc * s) * rlm1
                                      : (qs * c - qc * s) * rm * p.rinv + (ps * c - pc * s) * rlm1;
-        const double y = double(Y[l][m]);
+        const double y = double(q.Y[l][m]);
         Phi -= w * y * e;
         ar += w * y * dr;
         if constexpr (l >= 1) {
           T dY;
           if constexpr (m == 0) {
-            dY = T(kTab.e1[l][0]) * Y[l][1];
+            dY = T(kTab.e1[l][0]) * q.Y[l][1];
           } else if constexpr (m + 1 <= l) {
-            dY = T(kTab.e1[l][m]) * Y[l][m + 1] - T(kTab.e2[l][m]) * Y[l][m - 1];
+            dY = T(kTab.e1[l][m]) * q.Y[l][m + 1] - T(kTab.e2[l][m]) * q.Y[l][m - 1];
           } else {
-            dY = -T(kTab.e2[l][m]) * Y[l][m - 1];
+            dY = -T(kTab.e2[l][m]) * q.Y[l][m - 1];
           }
           at += w * double(dY) * eo;
           if constexpr (m >= 1) {
-            const T mYs = -(T(kTab.f1[l][m]) * Y[l + 1][m + 1] + T(kTab.f2[l][m]) * Y[l + 1][m - 1]);
+            const T mYs = -(T(kTab.f1[l][m]) * q.Y[l + 1][m + 1] + T(kTab.f2[l][m]) * q.Y[l + 1][m - 1]);
             ap += w * double(mYs) * f;
           }
         }
@@ -443,7 +497,8 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
     rl *= p.r;
     rm *= p.rinv;
   });
-  if (!valid) return;
+  if (!q.valid) return;
+  const uint32_t pidx = q.pidx;
   if (a.want_pot) a.pot[pidx] = Phi;
   if (a.want_acc) {
     const double st = double(p.st), ct = double(p.ct), cp = double(p.cp), sp = double(p.sp);
@@ -457,8 +512,9 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
 namespace {
 
 struct MexLayout {
-  size_t off_key0, off_key1, off_idx0, off_idx1, off_hist, off_tsum, off_toff, total;
-  int nblk, ntiles, lb;
+  size_t off_key0, off_key1, off_idx0, off_idx1, off_hist, off_tot, off_tsum, off_toff, off_bsum,
+      total;
+  int nblk, ntiles, nblocks, lb;
 };
 
 MexLayout mex_layout(int64_t n, int lmax) {
@@ -468,6 +524,7 @@ MexLayout mex_layout(int64_t n, int lmax) {
   if (L.nblk < 1) L.nblk = 1;
   L.ntiles = int((n + kMexTile - 1) / kMexTile);
   if (L.ntiles < 1) L.ntiles = 1;
+  L.nblocks = (L.ntiles + kMexBlockTiles - 1) / kMexBlockTiles;
   const size_t NC = size_t(mex_nc(L.lb));
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -481,16 +538,18 @@ MexLayout mex_layout(int64_t n, int lmax) {
   L.off_idx0 = take(nn * 4);
   L.off_idx1 = take(nn * 4);
   L.off_hist = take(size_t(256) * L.nblk * 4);
+  L.off_tot = take(size_t(256) * 4);
   L.off_tsum = take(size_t(L.ntiles) * 2 * NC * 8);
   L.off_toff = take(size_t(L.ntiles) * 2 * NC * 8);
+  L.off_bsum = take(size_t(L.nblocks) * 2 * NC * 8);
   L.total = o;
   return L;
 }
 
 template <typename T, int LB>
 int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
-  // largest LDS block: 256 rows x (2(2l+1) | 1) doubles at l = LB
-  const size_t lds = size_t(kMexTile) * ((2 * (2 * LB + 1)) | 1) * 8;
+  // largest LDS block: 2(2l+1) columns of kMexTile doubles at l = LB
+  const size_t lds = size_t(kMexTile) * (2 * (2 * LB + 1)) * 8;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(mex_tile_sums_kernel<T, LB>),
@@ -504,9 +563,10 @@ int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
   hipLaunchKernelGGL((mex_tile_sums_kernel<T, LB>), dim3(ntiles), dim3(kMexTile), lds, st, a);
   int rc = hip_fail(hipGetLastError(), "mex_tile_sums_kernel launch");
   if (rc) return rc;
-  const int ncol = 2 * (a.lmax + 1) * (a.lmax + 1);
-  hipLaunchKernelGGL((mex_tile_scan_kernel<LB>), dim3((ncol + 255) / 256), dim3(256), 0, st, a);
-  rc = hip_fail(hipGetLastError(), "mex_tile_scan_kernel launch");
+  hipLaunchKernelGGL((mex_block_sums_kernel<LB>), dim3(a.nblocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((mex_block_scan_kernel<LB>), dim3(1), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((mex_tile_offsets_kernel<LB>), dim3(a.nblocks), dim3(256), 0, st, a);
+  rc = hip_fail(hipGetLastError(), "mex tile offset launch");
   if (rc) return rc;
   rc = hook_before(st);
   if (rc) return rc;
@@ -517,8 +577,9 @@ int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
 
 template <typename T>
 int launch_mex_t(int lb, const double* x, const double* y, const double* z, const double* m,
-                 int64_t n, int lmax, const uint32_t* perm, double* tsum, double* toff, int ntiles,
-                 int outputs, double* pot, double* ax, double* ay, double* az, hipStream_t st) {
+                 int64_t n, int lmax, const uint32_t* perm, double* tsum, double* toff, double* bsum,
+                 int ntiles, int nblocks, int outputs, double* pot, double* ax, double* ay, double* az,
+                 hipStream_t st) {
   auto fill = [&](auto& a) {
     a.x = x;
     a.y = y;
@@ -528,6 +589,8 @@ int launch_mex_t(int lb, const double* x, const double* y, const double* z, cons
     a.perm = perm;
     a.tsum = tsum;
     a.toff = toff;
+    a.bsum = bsum;
+    a.nblocks = nblocks;
     a.pot = pot;
     a.ax = ax;
     a.ay = ay;
@@ -559,8 +622,10 @@ int launch_mex_force(const double* x, const double* y, const double* z, const do
   uint32_t* i0 = reinterpret_cast<uint32_t*>(base + L.off_idx0);
   uint32_t* i1 = reinterpret_cast<uint32_t*>(base + L.off_idx1);
   uint32_t* hist = reinterpret_cast<uint32_t*>(base + L.off_hist);
+  uint32_t* tot = reinterpret_cast<uint32_t*>(base + L.off_tot);
   double* tsum = reinterpret_cast<double*>(base + L.off_tsum);
   double* toff = reinterpret_cast<double*>(base + L.off_toff);
+  double* bsum = reinterpret_cast<double*>(base + L.off_bsum);
 
   hipLaunchKernelGGL(mex_keys_kernel, dim3(int((n + 255) / 256)), dim3(256), 0, st, x, y, z, n, k0, i0);
   int rc = hip_fail(hipGetLastError(), "mex_keys_kernel launch");
@@ -569,9 +634,9 @@ int launch_mex_force(const double* x, const double* y, const double* z, const do
     const int shift = 8 * pass;
     hipLaunchKernelGGL(radix_hist_kernel, dim3(L.nblk), dim3(kSortThreads), 0, st, k0, n, shift,
                        L.nblk, hist);
-    hipLaunchKernelGGL(radix_scan_kernel, dim3(1), dim3(1024), 0, st, hist, 256 * L.nblk);
+    hipLaunchKernelGGL(radix_digit_scan_kernel, dim3(256), dim3(256), 0, st, hist, L.nblk, tot);
     hipLaunchKernelGGL(radix_scatter_kernel, dim3(L.nblk), dim3(kSortThreads), 0, st, k0, i0, k1, i1,
-                       n, shift, L.nblk, hist);
+                       n, shift, L.nblk, hist, tot);
     rc = hip_fail(hipGetLastError(), "radix sort launch");
     if (rc) return rc;
     uint64_t* tk = k0;
@@ -583,10 +648,10 @@ int launch_mex_force(const double* x, const double* y, const double* z, const do
   }
   // after an even number of passes the sorted order is back in (k0, i0)
   if (prec == ETICS_FP64)
-    return launch_mex_t<double>(L.lb, x, y, z, m, n, lmax, i0, tsum, toff, L.ntiles, outputs, pot,
-                                ax, ay, az, st);
-  return launch_mex_t<float>(L.lb, x, y, z, m, n, lmax, i0, tsum, toff, L.ntiles, outputs, pot, ax,
-                             ay, az, st);
+    return launch_mex_t<double>(L.lb, x, y, z, m, n, lmax, i0, tsum, toff, bsum, L.ntiles, L.nblocks,
+                                outputs, pot, ax, ay, az, st);
+  return launch_mex_t<float>(L.lb, x, y, z, m, n, lmax, i0, tsum, toff, bsum, L.ntiles, L.nblocks,
+                             outputs, pot, ax, ay, az, st);
 }
 
 }  // namespace etics

@@ -172,3 +172,47 @@ def test_origin_and_axis_points(E, orc):
         d = np.sqrt((ax - rx) ** 2 + (ay - ry) ** 2 + (az - rz) ** 2)
         assert np.max(d[:4]) < tol * scale
         assert np.max(acc.pot_rel_err(pot[:4], rp[:4])) < tol
+
+
+def test_cfg1_full_size(E, orc):
+    """N = 10^4 Hernquist sphere at (10,6): every coefficient and every particle."""
+    p = W.make_config(1)
+    rA, rB = orc.scf_coeffs(p.x, p.y, p.z, p.m, 10, 6)
+    rp, rx, ry, rz = orc.scf_force(p.x, p.y, p.z, 10, 6, rA, rB)
+    for prec in (FP64, MIXED, COMP32):
+        A, B = gpu_coeffs(E, p, 10, 6, prec)
+        ce = acc.coeff_errors(A, B, rA, rB)
+        pot, ax, ay, az = gpu_force(E, p, 10, 6, A, B, prec)
+        ef = report(f"cfg1 full prec{prec} force", acc.force_rel_err(ax, ay, az, rx, ry, rz))
+        ep = report(f"cfg1 full prec{prec} pot", acc.pot_rel_err(pot, rp))
+        if prec == FP64:
+            assert ce["norm_rel"] < 1e-12 and ef["max"] < 1e-10 and ep["max"] < 1e-10
+        else:
+            assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4 and ep["median"] <= 1e-5 and ep["p99"] <= 1e-4
+
+
+def test_cfg3_full_size_sampled(E, orc):
+    """N = 10^7 (Hernquist + offset Plummer) at (20,14): the coefficients over all
+    particles against the oracle; forces on a seeded 10^5-particle sample."""
+    import torch
+    p = W.make_config(3)
+    n = p.x.shape[0]
+    rA, rB = orc.scf_coeffs(p.x, p.y, p.z, p.m, 20, 14)
+    idx = np.sort(np.random.default_rng(33).choice(n, 100_000, replace=False))
+    rp, rx, ry, rz = orc.scf_force(p.x[idx], p.y[idx], p.z[idx], 20, 14, rA, rB)
+    x, y, z, m = dev(p.x, p.y, p.z, p.m)
+    for prec in (FP64, COMP32, MIXED):
+        A, B = E.etics_scf_coeffs(x, y, z, m, 20, 14, prec)
+        pot, ax, ay, az = E.etics_scf_force(x, y, z, 20, 14, A, B, prec)
+        A, B = host(A, B)
+        ce = acc.coeff_errors(A, B, rA, rB)
+        it = torch.from_numpy(idx).cuda()
+        pot, ax, ay, az = (t[it].cpu().numpy() for t in (pot, ax, ay, az))
+        ef = report(f"cfg3 sampled prec{prec} force", acc.force_rel_err(ax, ay, az, rx, ry, rz))
+        ep = report(f"cfg3 sampled prec{prec} pot", acc.pot_rel_err(pot, rp))
+        print(f"cfg3 prec{prec} coeff {ce}", flush=True)
+        if prec == FP64:
+            assert ce["norm_rel"] < 1e-11 and ef["max"] < 1e-8 and ep["max"] < 1e-10
+        else:
+            assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4 and ep["median"] <= 1e-5 and ep["p99"] <= 1e-4
+        del pot, ax, ay, az
