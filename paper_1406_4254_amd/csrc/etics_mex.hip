@@ -246,31 +246,42 @@ __device__ __forceinline__ void mex_summands_col(const MexParticle<T>& p, const 
   });
 }
 
-// wavefront-wide sums of one FP64 value per lane, in a fixed shuffle tree
-__device__ __forceinline__ double wave_excl_prefix(double x, int lane) {
-  double incl = x;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double y = __shfl_up(incl, o);
-    if (lane >= o) incl += y;
-  }
-  const double ex = __shfl_up(incl, 1);
-  return lane == 0 ? 0.0 : ex;
+// Wavefront-wide sums of one FP64 value per lane with DPP lane moves (each 32-bit half
+// moved separately, zero where the source lane is out of range): a Hillis-Steele scan
+// inside each row of 16 lanes, then the row totals carried by the row broadcasts.  The
+// tree is fixed, so results do not depend on scheduling.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROW_MASK, 0xf, true);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned int>(lo)));
 }
-__device__ __forceinline__ double wave_excl_suffix(double x, int lane) {
-  double incl = x;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double y = __shfl_down(incl, o);
-    if (lane + o < 64) incl += y;
-  }
-  const double ex = __shfl_down(incl, 1);
-  return lane == 63 ? 0.0 : ex;
-}
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppWaveShr1 = 0x138, kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+// inclusive prefix over lanes 0..lane
+__device__ __forceinline__ double wave_incl_prefix(double x) {
+  x += dpp_move<kDppRowShr1, 0xf>(x);
+  x += dpp_move<kDppRowShr2, 0xf>(x);
+  x += dpp_move<kDppRowShr4, 0xf>(x);
+  x += dpp_move<kDppRowShr8, 0xf>(x);
+  x += dpp_move<kDppRowBcast15, 0xa>(x);  // last lane of rows 0, 2 into rows 1, 3
+  x += dpp_move<kDppRowBcast31, 0xc>(x);  // lane 31 into rows 2, 3
   return x;
+}
+// exclusive prefix over lanes 0..lane-1 (0 in lane 0)
+__device__ __forceinline__ double wave_excl_prefix(double x) {
+  return dpp_move<kDppWaveShr1, 0xf>(wave_incl_prefix(x));
+}
+// sum over the wavefront, the same in every lane
+__device__ __forceinline__ double wave_sum(double x) {
+  const long long b = __double_as_longlong(wave_incl_prefix(x));
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned int>(lo)));
 }
 
 template <typename T, int LB, int r>
@@ -333,12 +344,16 @@ __global__ __launch_bounds__(kMexTile) void mex_tile_sums_kernel(const MexArgs<L
     constexpr int W = 2 * (2 * l + 1), H = 2 * l + 1;
     mex_summands_col<T, LB, l, kMexTile>(q.p, q.Y, q.cm, q.sm, rl, rm, q.valid, S + t);
     __syncthreads();
-    // one wavefront per column: two rows per lane, then a shuffle tree
-    for (int c = wave; c < W; c += kMexTile / 64) {
-      const double2 v = *reinterpret_cast<const double2*>(S + c * kMexTile + 2 * lane);
-      const double tot = wave_sum(v.x + v.y);
-      if (lane == 0) out[(c < H ? 0 : NC) + mex_coff(l) + (c < H ? c : c - H)] = tot;
-    }
+    // one wavefront per column: two rows per lane, then a lane tree; the columns of a
+    // wavefront are independent and unrolled so their trees interleave
+    static_for<(W + 1) / 2>([&](auto jc) {
+      const int c = 2 * decltype(jc)::value + wave;
+      if (c < W) {
+        const double2 v = *reinterpret_cast<const double2*>(S + c * kMexTile + 2 * lane);
+        const double tot = wave_sum(v.x + v.y);
+        if (lane == 0) out[(c < H ? 0 : NC) + mex_coff(l) + (c < H ? c : c - H)] = tot;
+      }
+    });
     __syncthreads();
     rl *= q.p.r;
     rm *= q.p.rinv;
@@ -362,22 +377,33 @@ __global__ __launch_bounds__(256) void mex_block_sums_kernel(const MexArgs<LB> a
   }
 }
 
-// step 2: exclusive prefix (inward) / suffix (outward) over the blocks, in place
+// step 2: exclusive prefix (inward) / suffix (outward) over the blocks, in place; one
+// wavefront per column: lane k takes a run of consecutive blocks (in scan order: forward
+// for inward, backward for outward), then a lane tree gives the runs before it
 template <int LB>
 __global__ __launch_bounds__(256) void mex_block_scan_kernel(const MexArgs<LB> a) {
   constexpr int NC = mex_nc(LB);
   const int ncu = (a.lmax + 1) * (a.lmax + 1);
-  for (int c = threadIdx.x; c < 2 * ncu; c += blockDim.x) {
-    const int side = c < ncu ? 0 : 1;
-    const int comp = side == 0 ? c : c - ncu;
-    double run = 0.0;
-    for (int k = 0; k < a.nblocks; ++k) {
-      const int b = side == 0 ? k : a.nblocks - 1 - k;
-      double* e = a.bsum + (size_t(b) * 2 + side) * NC + comp;
-      const double v = *e;
-      *e = run;
-      run += v;
-    }
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= 2 * ncu) return;  // whole wavefronts leave together
+  const int side = c < ncu ? 0 : 1;
+  const int comp = side == 0 ? c : c - ncu;
+  const int nb = a.nblocks;
+  const int run = (nb + 63) / 64;
+  auto at = [&](int k) {  // k-th block in scan order
+    const int b = side == 0 ? k : nb - 1 - k;
+    return a.bsum + (size_t(b) * 2 + side) * NC + comp;
+  };
+  const int k0 = lane * run;
+  double tot = 0.0;
+  for (int k = k0; k < k0 + run && k < nb; ++k) tot += *at(k);
+  double acc = wave_excl_prefix(tot);
+  for (int k = k0; k < k0 + run && k < nb; ++k) {
+    double* e = at(k);
+    const double v = *e;
+    *e = acc;
+    acc += v;
   }
 }
 
@@ -426,27 +452,27 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
     constexpr int W = 2 * (2 * l + 1), H = 2 * l + 1;
     mex_summands_col<T, LB, l, kMexTile>(p, q.Y, q.cm, q.sm, rl, rm, q.valid, S + t);
     __syncthreads();
-    // exclusive scans of every column inside the tile, one wavefront per column (two
-    // rows per lane, then a shuffle tree across lanes); inward columns run forward,
-    // outward columns backward; the tile's offset from the other tiles is added
-    for (int c = wave; c < W; c += kMexTile / 64) {
-      const bool fwd = c < H;
-      double* cp = S + c * kMexTile + 2 * lane;
-      const double2 v = *reinterpret_cast<const double2*>(cp);
-      const double off = offs[(fwd ? 0 : NC) + mex_coff(l) + (fwd ? c : c - H)];
-      double e0, e1, before;
-      if (fwd) {
-        e0 = 0.0;
-        e1 = v.x;
-        before = wave_excl_prefix(v.x + v.y, lane);
-      } else {
-        e1 = 0.0;
-        e0 = v.y;
-        before = wave_excl_suffix(v.y + v.x, lane);
+    // exclusive scans of every column inside the tile, one wavefront per column: lane k
+    // takes two consecutive rows, then a lane tree gives what the lanes before it hold.
+    // Inward columns run forward (lane k: rows 2k, 2k+1); outward columns backward (lane
+    // k: rows 126-2k, 127-2k, so the lanes before k hold the later particles).  The
+    // tile's offset from the other tiles is added.  Columns are unrolled so that their
+    // trees interleave.
+    static_for<(W + 1) / 2>([&](auto jc) {
+      const int c = 2 * decltype(jc)::value + wave;
+      if (c < W) {
+        const bool fwd = c < H;
+        double* cp = S + c * kMexTile + (fwd ? 2 * lane : kMexTile - 2 - 2 * lane);
+        const double2 v = *reinterpret_cast<const double2*>(cp);
+        const double off = offs[(fwd ? 0 : NC) + mex_coff(l) + (fwd ? c : c - H)];
+        // within the pair: the first row in scan order gets 0, the second the first
+        const double first = fwd ? v.x : v.y, second = fwd ? v.y : v.x;
+        const double base = off + wave_excl_prefix(first + second);
+        const double r_first = base, r_second = base + first;
+        *reinterpret_cast<double2*>(cp) =
+            fwd ? make_double2(r_first, r_second) : make_double2(r_second, r_first);
       }
-      const double base = off + before;
-      *reinterpret_cast<double2*>(cp) = make_double2(base + e0, base + e1);
-    }
+    });
     __syncthreads();
     // synthesis of this l from the particle's own q (components 0..2l) and p (2l+1..)
     {
@@ -564,7 +590,8 @@ int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
   int rc = hip_fail(hipGetLastError(), "mex_tile_sums_kernel launch");
   if (rc) return rc;
   hipLaunchKernelGGL((mex_block_sums_kernel<LB>), dim3(a.nblocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL((mex_block_scan_kernel<LB>), dim3(1), dim3(256), 0, st, a);
+  const int ncol = 2 * (a.lmax + 1) * (a.lmax + 1);
+  hipLaunchKernelGGL((mex_block_scan_kernel<LB>), dim3((ncol + 3) / 4), dim3(256), 0, st, a);
   hipLaunchKernelGGL((mex_tile_offsets_kernel<LB>), dim3(a.nblocks), dim3(256), 0, st, a);
   rc = hip_fail(hipGetLastError(), "mex tile offset launch");
   if (rc) return rc;
