@@ -146,12 +146,14 @@ int etics_scf_force_batched(const double* x, const double* y, const double* z,
    feeling only its own SCF field (the paper integrates with a leapfrog, Section
    3.4):  v += dt/2 a(x);  x += dt v;  a = a(x);  v += dt/2 a.  x..vz are updated in
    place; m and offsets are as for the batched calls.  Every call first computes
-   a(x) at the current positions (one extra force calculation), then runs the steps.
-   Unless ETICS_LEAPFROG_EAGER is set, one step is captured into a hipGraph on a
-   library stream (the first time for a given set of pointers, sizes, precision, dt
-   and workspace; a different set replaces the cached graph) and replayed nsteps
-   times on `stream`; graph and eager runs launch the same kernels with the same
-   arguments, so they give bitwise-equal results.  The cache is shared by all threads
+   a(x) at the current positions (one extra force calculation), then runs the steps;
+   each step's closing kick (and the next step's opening kick and drift) is applied
+   per particle by the force kernel.  Unless ETICS_LEAPFROG_EAGER is set, one step is
+   captured into a hipGraph on a library stream (the first time for a given set of
+   pointers, sizes, precision, dt and workspace; a different set replaces the cached
+   graph) and replayed nsteps-1 times on `stream`, followed by the last step launched
+   directly; graph and eager runs launch the same kernels with the same arguments, so
+   they give bitwise-equal results.  The cache is shared by all threads
    of the process (calls are serialised by a lock).  nsteps = 0 does nothing. */
 int etics_leapfrog_scf_batched(double* x, double* y, double* z, double* vx, double* vy, double* vz,
                                const double* m, const int64_t* offsets, int nsys, int64_t ntotal,

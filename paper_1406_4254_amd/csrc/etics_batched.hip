@@ -10,8 +10,13 @@
 //
 // Leapfrog (the paper integrates with a leapfrog, Section 3.4), kick-drift-kick:
 //   v += dt/2 a(x);  x += dt v;  a = a(x);  v += dt/2 a.
-// One step (kick+drift, coefficients, reduction, coefficient rescale, force, kick) is
-// captured once into a hipGraph and replayed; the capture is cached per argument set.
+// The first opening kick and drift run as their own kernel; after that, the batched
+// force kernel applies each particle's closing kick and, except in the last step, the
+// next step's opening kick and drift as soon as its acceleration is known, so a step is
+// coefficients, reduction, coefficient rescale and force.  Steps 1 .. nsteps-1 are
+// captured once into a hipGraph and replayed (the capture is cached per argument set);
+// the last step runs directly.  Every kick and drift is one FP64 fused multiply-add per
+// component in both kernels, so eager and graph runs give identical bits.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -75,30 +80,15 @@ __global__ __launch_bounds__(256) void lf_kick_drift_kernel(double* __restrict__
                                                             int64_t n, double hdt, double dt) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
-    const double ux = vx[i] + hdt * ax[i];
-    const double uy = vy[i] + hdt * ay[i];
-    const double uz = vz[i] + hdt * az[i];
+    const double ux = __builtin_fma(hdt, ax[i], vx[i]);
+    const double uy = __builtin_fma(hdt, ay[i], vy[i]);
+    const double uz = __builtin_fma(hdt, az[i], vz[i]);
     vx[i] = ux;
     vy[i] = uy;
     vz[i] = uz;
-    x[i] += dt * ux;
-    y[i] += dt * uy;
-    z[i] += dt * uz;
-  }
-}
-
-__global__ __launch_bounds__(256) void lf_kick_kernel(double* __restrict__ vx,
-                                                      double* __restrict__ vy,
-                                                      double* __restrict__ vz,
-                                                      const double* __restrict__ ax,
-                                                      const double* __restrict__ ay,
-                                                      const double* __restrict__ az, int64_t n,
-                                                      double hdt) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    vx[i] += hdt * ax[i];
-    vy[i] += hdt * ay[i];
-    vz[i] += hdt * az[i];
+    x[i] = __builtin_fma(dt, ux, x[i]);
+    y[i] = __builtin_fma(dt, uy, y[i]);
+    z[i] = __builtin_fma(dt, uz, z[i]);
   }
 }
 
@@ -189,20 +179,28 @@ int accelerations(const LeapfrogCall& c, const CoeffPlan& plan, const Parts& p, 
                                   p.az, p.prep, st);
 }
 
-int one_step(const LeapfrogCall& c, const CoeffPlan& plan, const Parts& p, hipStream_t st) {
-  const double hdt = 0.5 * c.dt;
+// the opening kick and drift of the first step, from the accelerations in p.ax..p.az
+int first_kick_drift(const LeapfrogCall& c, const Parts& p, hipStream_t st) {
   int64_t grid = (c.ntotal + 255) / 256;
   if (grid > 8192) grid = 8192;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(lf_kick_drift_kernel, dim3(int(grid)), dim3(256), 0, st, c.x, c.y, c.z, c.vx,
-                     c.vy, c.vz, p.ax, p.ay, p.az, c.ntotal, hdt, c.dt);
-  int rc = hip_fail(hipGetLastError(), "lf_kick_drift_kernel launch");
+                     c.vy, c.vz, p.ax, p.ay, p.az, c.ntotal, 0.5 * c.dt, c.dt);
+  return hip_fail(hipGetLastError(), "lf_kick_drift_kernel launch");
+}
+
+// The rest of a step once x has drifted: a(x) from this step's coefficients, the closing
+// kick and, unless it is the last step (last = true), the next step's opening kick and
+// drift, all in the force kernel (KDK: v += dt/2 a; x += dt v; a = a(x); v += dt/2 a).
+int step_tail(const LeapfrogCall& c, const CoeffPlan& plan, const Parts& p, bool last,
+              hipStream_t st) {
+  int rc = launch_scf_coeffs_batched(plan, c.x, c.y, c.z, c.m, c.offsets, p.ustart, p.usys, c.nsys,
+                                     c.ntotal, p.A, p.B, p.partials, st);
   if (rc) return rc;
-  rc = accelerations(c, plan, p, st);
-  if (rc) return rc;
-  hipLaunchKernelGGL(lf_kick_kernel, dim3(int(grid)), dim3(256), 0, st, c.vx, c.vy, c.vz, p.ax, p.ay,
-                     p.az, c.ntotal, hdt);
-  return hip_fail(hipGetLastError(), "lf_kick_kernel launch");
+  LfUpdate lf{c.x, c.y, c.z, c.vx, c.vy, c.vz, 0.5 * c.dt, c.dt, last ? 1 : 2};
+  return launch_scf_force_batched(c.x, c.y, c.z, c.offsets, p.ustart, p.usys, c.nsys, c.ntotal,
+                                  c.nmax, c.lmax, p.A, p.B, c.prec, ETICS_ACC, nullptr, p.ax, p.ay,
+                                  p.az, p.prep, st, &lf);
 }
 
 struct GraphCache {
@@ -247,14 +245,18 @@ int run_leapfrog(double* x, double* y, double* z, double* vx, double* vy, double
   const Parts p = parts_of(c);
   rc = launch_units(offsets, nsys, ntotal, p.ustart, p.usys, st);
   if (rc) return rc;
+  if (nsteps < 1) return ETICS_OK;
   rc = accelerations(c, plan, p, st);  // a(x) at the start of the first step
   if (rc) return rc;
-  if (flags & ETICS_LEAPFROG_EAGER) {
-    for (int k = 0; k < nsteps; ++k) {
-      rc = one_step(c, plan, p, st);
+  rc = first_kick_drift(c, p, st);
+  if (rc) return rc;
+  // steps 1 .. nsteps-1 end with the next step's kick and drift; the last one does not
+  if ((flags & ETICS_LEAPFROG_EAGER) || nsteps == 1) {
+    for (int k = 1; k < nsteps; ++k) {
+      rc = step_tail(c, plan, p, false, st);
       if (rc) return rc;
     }
-    return ETICS_OK;
+    return step_tail(c, plan, p, true, st);
   }
   std::lock_guard<std::mutex> lock(g_graph_mutex);
   if (!g_graph.valid || !same_call(g_graph.call, c)) {
@@ -267,7 +269,7 @@ int run_leapfrog(double* x, double* y, double* z, double* vx, double* vy, double
     rc = hip_fail(hipStreamBeginCapture(g_graph.capture, hipStreamCaptureModeThreadLocal),
                   "hipStreamBeginCapture");
     if (rc) return rc;
-    const int rs = one_step(c, plan, p, g_graph.capture);
+    const int rs = step_tail(c, plan, p, false, g_graph.capture);
     hipGraph_t graph = nullptr;
     rc = hip_fail(hipStreamEndCapture(g_graph.capture, &graph), "hipStreamEndCapture");
     if (rs) {
@@ -284,11 +286,11 @@ int run_leapfrog(double* x, double* y, double* z, double* vx, double* vy, double
     g_graph.call = c;
     g_graph.valid = true;
   }
-  for (int k = 0; k < nsteps; ++k) {
+  for (int k = 1; k < nsteps; ++k) {
     rc = hip_fail(hipGraphLaunch(g_graph.exec, st), "hipGraphLaunch");
     if (rc) return rc;
   }
-  return ETICS_OK;
+  return step_tail(c, plan, p, true, st);
 }
 
 }  // namespace etics

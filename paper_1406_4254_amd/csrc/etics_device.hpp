@@ -16,7 +16,8 @@ constexpr BasisTables<double> kTab = make_tables<double>();
 
 __device__ __forceinline__ float rcp_(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double rcp_(double v) { return 1.0 / v; }
-__device__ __forceinline__ float sqrt_(float v) { return __builtin_sqrtf(v); }
+// FP32: the hardware square root (about 1 ulp), without the correctly-rounded fix-up
+__device__ __forceinline__ float sqrt_(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ __forceinline__ double sqrt_(double v) { return __builtin_sqrt(v); }
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }

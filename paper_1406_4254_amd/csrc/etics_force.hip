@@ -70,6 +70,7 @@ struct ForceArgs {
   double *pot, *ax, *ay, *az;
   int K, nmax, lmax;
   int want_pot;
+  LfUpdate lf;     // lf.mode = 0: write a; otherwise update v (and x) instead
 };
 
 // potential / acceleration of point i from one system's prepared coefficients cf
@@ -223,9 +224,29 @@ __device__ __forceinline__ void force_point(const ForceArgs& a, const T* __restr
       const T gx = s.st * s.cp * accR + s.ct * s.cp * accT - s.sp * accF;
       const T gy = s.st * s.sp * accR + s.ct * s.sp * accT + s.cp * accF;
       const T gz = s.ct * accR - s.st * accT;
-      a.ax[i] = double(gx);
-      a.ay[i] = double(gy);
-      a.az[i] = double(gz);
+      if (a.lf.mode == 0) {
+        a.ax[i] = double(gx);
+        a.ay[i] = double(gy);
+        a.az[i] = double(gz);
+      } else {
+        // leapfrog: closing kick, then (mode 2) the next step's opening kick and drift;
+        // only this thread touches particle i, so x is updated in place after its use
+        const double h = a.lf.h;
+        double vx = __builtin_fma(h, double(gx), a.lf.vx[i]);
+        double vy = __builtin_fma(h, double(gy), a.lf.vy[i]);
+        double vz = __builtin_fma(h, double(gz), a.lf.vz[i]);
+        if (a.lf.mode == 2) {
+          vx = __builtin_fma(h, double(gx), vx);
+          vy = __builtin_fma(h, double(gy), vy);
+          vz = __builtin_fma(h, double(gz), vz);
+          a.lf.x[i] = __builtin_fma(a.lf.dt, vx, a.x[i]);
+          a.lf.y[i] = __builtin_fma(a.lf.dt, vy, a.y[i]);
+          a.lf.z[i] = __builtin_fma(a.lf.dt, vz, a.z[i]);
+        }
+        a.lf.vx[i] = vx;
+        a.lf.vy[i] = vy;
+        a.lf.vz[i] = vz;
+      }
     }
   }
 }
@@ -362,10 +383,11 @@ int launch_scf_force_batched(const double* x, const double* y, const double* z,
                              const int64_t* offsets, const int* ustart, const int* usys, int nsys,
                              int64_t ntotal, int nmax, int lmax, const double* A, const double* B,
                              int prec, int outputs, double* pot, double* ax, double* ay,
-                             double* az, void* prep, hipStream_t st) {
+                             double* az, void* prep, hipStream_t st, const LfUpdate* lf) {
   int rc = launch_prep(A, B, nmax, lmax, nsys, prec, prep, st);
   if (rc || ntotal == 0) return rc;
-  const ForceArgs a = make_force_args(x, y, z, ntotal, nmax, lmax, outputs, pot, ax, ay, az, prep);
+  ForceArgs a = make_force_args(x, y, z, ntotal, nmax, lmax, outputs, pot, ax, ay, az, prep);
+  if (lf) a.lf = *lf;
   const BatchInfo bi{offsets, ustart, usys, nsys};
   return launch_force_any(a, prec, outputs, max_units(ntotal, nsys), &bi, st);
 }

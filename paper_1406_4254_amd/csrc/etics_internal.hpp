@@ -67,11 +67,21 @@ int launch_scf_coeffs_batched(const CoeffPlan& p, const double* x, const double*
                               const double* m, const int64_t* offsets, const int* ustart,
                               const int* usys, int nsys, int64_t ntotal, double* A, double* B,
                               void* partials, hipStream_t st);
+// Leapfrog update applied by the batched force kernel to each particle right after its
+// acceleration a is known, instead of storing a: mode 1 = closing kick v += h a;
+// mode 2 = closing kick, then the next step's opening kick v += h a and drift
+// x += dt v.  Each operation is one FP64 fused multiply-add, as in the separate kernels.
+struct LfUpdate {
+  double *x, *y, *z, *vx, *vy, *vz;
+  double h, dt;
+  int mode;
+};
+
 int launch_scf_force_batched(const double* x, const double* y, const double* z,
                              const int64_t* offsets, const int* ustart, const int* usys, int nsys,
                              int64_t ntotal, int nmax, int lmax, const double* A, const double* B,
                              int prec, int outputs, double* pot, double* ax, double* ay,
-                             double* az, void* prep, hipStream_t st);
+                             double* az, void* prep, hipStream_t st, const LfUpdate* lf = nullptr);
 
 struct BatchedLayout {
   size_t off_ustart, off_usys, off_partials, off_prep, off_A, off_B, off_acc, total;
