@@ -40,19 +40,20 @@ struct CoeffArgs {
 };
 
 // ------------------------------------------------------------ phase-1 job plan
-// Greedy longest-job-first split of the basis jobs of a cutoff bucket between the
-// four wavefronts.  Angular job m costs ~6 operations per l in [m, lb]; radial job l
-// ~2 operations per padded radial order.
-template <int LB, int NRP>
+// Greedy longest-job-first split of the basis jobs of a cutoff bucket between the NW
+// wavefronts that share a group of 64 particles (NW = 4: the whole workgroup; NW = 2 or
+// 1: two or four groups, so a tile holds 128 or 256 particles).  Angular job m costs ~6
+// operations per l in [m, lb]; radial job l ~2 operations per padded radial order.
+template <int LB, int NRP, int NW>
 struct JobPlan {
   int ownerZ[LB + 1];
   int ownerG[LB + 1];
-  int maxm[4];
+  int maxm[NW];
 };
 
-template <int LB, int NRP>
-constexpr JobPlan<LB, NRP> make_job_plan() {
-  JobPlan<LB, NRP> p{};
+template <int LB, int NRP, int NW>
+constexpr JobPlan<LB, NRP, NW> make_job_plan() {
+  JobPlan<LB, NRP, NW> p{};
   int code[2 * (LB + 1)] = {};
   int cost[2 * (LB + 1)] = {};
   int nj = 0;
@@ -73,11 +74,11 @@ constexpr JobPlan<LB, NRP> make_job_plan() {
       code[j] = code[j - 1];
       code[j - 1] = c;
     }
-  int load[4] = {0, 0, 0, 0};
-  for (int w = 0; w < 4; ++w) p.maxm[w] = -1;
+  int load[NW] = {};
+  for (int w = 0; w < NW; ++w) p.maxm[w] = -1;
   for (int i = 0; i < nj; ++i) {
     int w = 0;
-    for (int k = 1; k < 4; ++k)
+    for (int k = 1; k < NW; ++k)
       if (load[k] < load[w]) w = k;
     load[w] += cost[i];
     if (code[i] & 0x80) {
@@ -171,8 +172,9 @@ __device__ __forceinline__ void decode_block(int b, int lmax, int nchunks, int& 
 
 // One workgroup's share of the coefficient sums: the LDS tile, the register block
 // of each lane, and the three steps (basis -> LDS, accumulate, merge and write).
-template <typename T, int LB, int NB, int BS, int MODE>
+template <typename T, int LB, int NB, int BS, int MODE, int NW>
 struct CoeffWG {
+  static_assert(NW == 1 || NW == 2 || NW == 4, "wavefronts per particle group");
   static constexpr int NRP = nrp_for_nb(NB);
   static constexpr int SPG = g_stride(LB, NRP);
   static constexpr int SPZ = z_stride(LB, BS);
@@ -180,7 +182,7 @@ struct CoeffWG {
 
   T* G;  // [tp][SPG]  radial values, rows of NRP per l
   T* Z;  // [tp][SPZ]  angular values x mass x radial prefactor
-  int tid, lane, wave, maxm_w, lmax, nmax, tp, streams, nblocks, nchunks;
+  int tid, lane, wave, rank, pidx, maxm_w, lmax, nmax, tp, streams, nblocks, nchunks;
   int my_stream, my_block, bl, n0, s0;
   bool active;
   T acc[NB][BS];
@@ -188,12 +190,14 @@ struct CoeffWG {
 
   __device__ __forceinline__ void init(unsigned char* lds, int tp_, int lmax_, int nmax_,
                                        int nblocks_, int streams_, int nchunks_) {
-    constexpr JobPlan<LB, NRP> kJP = make_job_plan<LB, NRP>();
+    constexpr JobPlan<LB, NRP, NW> kJP = make_job_plan<LB, NRP, NW>();
     G = reinterpret_cast<T*>(lds);
     Z = G + tp_ * SPG;
     tid = threadIdx.x;
     lane = tid & 63;
     wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    rank = wave % NW;               // job share within the particle group
+    pidx = (wave / NW) * 64 + lane;  // this lane's particle in the tile (phase 1)
     tp = tp_;
     lmax = lmax_;
     nmax = nmax_;
@@ -202,8 +206,8 @@ struct CoeffWG {
     nchunks = nchunks_;
     // largest angular column owned by this wavefront (the diagonal walk stops there)
     maxm_w = -1;
-    static_for<4>([&](auto wc) {
-      if (wave == decltype(wc)::value) maxm_w = kJP.maxm[decltype(wc)::value];
+    static_for<NW>([&](auto wc) {
+      if (rank == decltype(wc)::value) maxm_w = kJP.maxm[decltype(wc)::value];
     });
     my_stream = tid / nblocks;
     my_block = tid - my_stream * nblocks;
@@ -242,12 +246,12 @@ struct CoeffWG {
 
   // phase 1: basis of the particle of this lane (zero mass for an empty lane)
   __device__ __forceinline__ void phase1(double xd, double yd, double zd, double md) {
-    constexpr JobPlan<LB, NRP> kJP = make_job_plan<LB, NRP>();
-    if (lane >= tp) return;
+    constexpr JobPlan<LB, NRP, NW> kJP = make_job_plan<LB, NRP, NW>();
+    if (pidx >= tp) return;
     const Sph<T> s = sph<T>(xd, yd, zd);
     const T tu = s.t * s.u, ctu = s.ct * tu, tu2 = tu * tu, stu = s.st * tu;
-    T* Gp = G + lane * SPG;
-    T* Zp = Z + lane * SPZ;
+    T* Gp = G + pidx * SPG;
+    T* Zp = Z + pidx * SPZ;
     // angular jobs: column m of mass u (tu)^l Ybar_lm (cos, sin)(m phi), l = m..lmax.
     // The diagonal value mass u (tu)^m Ybar_mm and (cos, sin)(m phi) are walked up to
     // the largest column this wavefront owns.
@@ -263,7 +267,7 @@ struct CoeffWG {
           cmc = c2;
         }
       }
-      if (wave == kJP.ownerZ[m] && m <= lmax) {
+      if (rank == kJP.ownerZ[m] && m <= lmax) {
         T P2 = T(0), P1 = Pd;
         auto put = [&](auto lc2, T P) {
           constexpr int l = decltype(lc2)::value;
@@ -289,7 +293,7 @@ struct CoeffWG {
     // nmax only feed coefficients that are never written out; they stay finite.
     static_for<LB + 1>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
-      if (wave == kJP.ownerG[l] && l <= lmax) {
+      if (rank == kJP.ownerG[l] && l <= lmax) {
         T p2 = T(1), p1 = T(0);
         static_for<NRP / 4>([&](auto qc) {
           constexpr int nb4 = 4 * decltype(qc)::value;
@@ -411,11 +415,11 @@ struct CoeffWG {
   }
 };
 
-template <typename T, int LB, int NB, int BS, int MODE>
+template <typename T, int LB, int NB, int BS, int MODE, int NW>
 __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coeff_kernel(
     const CoeffArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  CoeffWG<T, LB, NB, BS, MODE> w;
+  CoeffWG<T, LB, NB, BS, MODE, NW> w;
   w.init(lds_raw, a.tp, a.lmax, a.nmax, a.nblocks, a.streams, a.nchunks);
   w.zero_slots();
   __syncthreads();
@@ -427,8 +431,8 @@ __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coe
   // particle data of the first tile (later tiles are prefetched during phase 2)
   double xd = 0.0, yd = 0.0, zd = 0.0, md = 0.0;
   auto load_particle = [&](int tile) {
-    const int64_t pi = int64_t(tile) * a.tp + w.lane;
-    const bool valid = tile < t1 && w.lane < a.tp && pi < a.n;
+    const int64_t pi = int64_t(tile) * a.tp + w.pidx;
+    const bool valid = tile < t1 && w.pidx < a.tp && pi < a.n;
     xd = valid ? a.x[pi] : 0.0;
     yd = valid ? a.y[pi] : 0.0;
     zd = valid ? a.z[pi] : 0.0;
@@ -449,7 +453,7 @@ __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coe
     __syncthreads();
   }
   w.fold();
-  using PT = typename CoeffWG<T, LB, NB, BS, MODE>::PT;
+  using PT = typename CoeffWG<T, LB, NB, BS, MODE, NW>::PT;
   w.merge_write(lds_raw, reinterpret_cast<PT*>(a.partials) + size_t(blockIdx.x) * 2 * a.K, a.K);
 }
 
@@ -464,14 +468,14 @@ struct BatchedCoeffArgs {
   const int* usys;    // [units] system of each unit
   int64_t ntotal;
   void* partials;     // [units][2K]
-  int nsys, K, nmax, lmax, tp, nblocks, streams, nchunks;
+  int nsys, K, nmax, lmax, tp, nblocks, streams, nchunks, flush_tiles;
 };
 
-template <typename T, int LB, int NB, int BS, int MODE>
+template <typename T, int LB, int NB, int BS, int MODE, int NW>
 __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coeff_batched_kernel(
     const BatchedCoeffArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  using W = CoeffWG<T, LB, NB, BS, MODE>;
+  using W = CoeffWG<T, LB, NB, BS, MODE, NW>;
   W w;
   w.init(lds_raw, a.tp, a.lmax, a.nmax, a.nblocks, a.streams, a.nchunks);
   const int nunits = a.ustart[a.nsys];
@@ -486,13 +490,18 @@ __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coe
     w.zero_slots();
     w.clear_wide();
     __syncthreads();
+    int tcount = 0;
     for (int tile = 0; tile < ntiles; ++tile) {
-      const int64_t pi = ub + int64_t(tile) * a.tp + w.lane;
-      const bool valid = w.lane < a.tp && pi < ue;
+      const int64_t pi = ub + int64_t(tile) * a.tp + w.pidx;
+      const bool valid = w.pidx < a.tp && pi < ue;
       w.phase1(valid ? a.x[pi] : 0.0, valid ? a.y[pi] : 0.0, valid ? a.z[pi] : 0.0,
                valid ? a.m[pi] : 0.0);
       __syncthreads();
       w.phase2();
+      if (++tcount == a.flush_tiles) {
+        tcount = 0;
+        w.fold();
+      }
       __syncthreads();
     }
     w.fold();
@@ -595,13 +604,13 @@ double anl_tilde(int n, int l) {
 
 namespace {
 
-template <bool BATCHED, typename T, int LB, int NB, int BS, int MODE, typename Args>
+template <bool BATCHED, typename T, int LB, int NB, int BS, int MODE, int NW, typename Args>
 int launch_coeff_t(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
   const void* kfn;
   if constexpr (BATCHED)
-    kfn = reinterpret_cast<const void*>(scf_coeff_batched_kernel<T, LB, NB, BS, MODE>);
+    kfn = reinterpret_cast<const void*>(scf_coeff_batched_kernel<T, LB, NB, BS, MODE, NW>);
   else
-    kfn = reinterpret_cast<const void*>(scf_coeff_kernel<T, LB, NB, BS, MODE>);
+    kfn = reinterpret_cast<const void*>(scf_coeff_kernel<T, LB, NB, BS, MODE, NW>);
   static bool attr_set = false;
   if (!attr_set) {
     // the kernel has no static LDS: the whole 160 KiB of a CU may be requested
@@ -612,22 +621,33 @@ int launch_coeff_t(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) 
   int rc = hook_before(st);
   if (rc) return rc;
   if constexpr (BATCHED)
-    hipLaunchKernelGGL((scf_coeff_batched_kernel<T, LB, NB, BS, MODE>), dim3(grid), dim3(kCoeffThreads),
-                       p.lds_bytes, st, a);
+    hipLaunchKernelGGL((scf_coeff_batched_kernel<T, LB, NB, BS, MODE, NW>), dim3(grid),
+                       dim3(kCoeffThreads), p.lds_bytes, st, a);
   else
-    hipLaunchKernelGGL((scf_coeff_kernel<T, LB, NB, BS, MODE>), dim3(grid), dim3(kCoeffThreads),
+    hipLaunchKernelGGL((scf_coeff_kernel<T, LB, NB, BS, MODE, NW>), dim3(grid), dim3(kCoeffThreads),
                        p.lds_bytes, st, a);
   rc = hip_fail(hipGetLastError(), "scf_coeff_kernel launch");
   return rc ? rc : hook_after(st);
 }
 
-template <bool BATCHED, typename T, int MODE, int LB, typename Args>
+template <bool BATCHED, typename T, int MODE, int LB, int NW, typename Args>
 int launch_coeff_nb(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
   switch (p.nb) {
-    case 9: return launch_coeff_t<BATCHED, T, LB, 9, 4, MODE>(p, a, grid, st);
-    case 11: return launch_coeff_t<BATCHED, T, LB, 11, 4, MODE>(p, a, grid, st);
-    default: return launch_coeff_t<BATCHED, T, LB, 12, 4, MODE>(p, a, grid, st);
+    case 9: return launch_coeff_t<BATCHED, T, LB, 9, 4, MODE, NW>(p, a, grid, st);
+    case 11: return launch_coeff_t<BATCHED, T, LB, 11, 4, MODE, NW>(p, a, grid, st);
+    default: return launch_coeff_t<BATCHED, T, LB, 12, 4, MODE, NW>(p, a, grid, st);
   }
+}
+
+// particle groups per tile: only the small cutoff buckets have the LDS for 128 or 256
+// particles per tile
+template <bool BATCHED, typename T, int MODE, int LB, typename Args>
+int launch_coeff_nw(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
+  if constexpr (LB <= 6) {
+    if (p.nw == 1) return launch_coeff_nb<BATCHED, T, MODE, LB, 1>(p, a, grid, st);
+    if (p.nw == 2) return launch_coeff_nb<BATCHED, T, MODE, LB, 2>(p, a, grid, st);
+  }
+  return launch_coeff_nb<BATCHED, T, MODE, LB, 4>(p, a, grid, st);
 }
 
 template <bool BATCHED, typename Args>
@@ -635,10 +655,10 @@ int launch_coeff_any(const CoeffPlan& p, const Args& a, int grid, hipStream_t st
   const int mode = p.prec == ETICS_FP64 ? 0 : (p.prec == ETICS_MIXED_FP64ACC ? 1 : 2);
 #define ETICS_LB_CASES(T, MODE)                                                  \
   switch (p.lb) {                                                                \
-    case 2: return launch_coeff_nb<BATCHED, T, MODE, 2>(p, a, grid, st);         \
-    case 6: return launch_coeff_nb<BATCHED, T, MODE, 6>(p, a, grid, st);         \
-    case 10: return launch_coeff_nb<BATCHED, T, MODE, 10>(p, a, grid, st);       \
-    default: return launch_coeff_nb<BATCHED, T, MODE, 14>(p, a, grid, st);       \
+    case 2: return launch_coeff_nw<BATCHED, T, MODE, 2>(p, a, grid, st);         \
+    case 6: return launch_coeff_nw<BATCHED, T, MODE, 6>(p, a, grid, st);         \
+    case 10: return launch_coeff_nw<BATCHED, T, MODE, 10>(p, a, grid, st);       \
+    default: return launch_coeff_nw<BATCHED, T, MODE, 14>(p, a, grid, st);       \
   }
   if (mode == 0) {
     ETICS_LB_CASES(double, 0)
@@ -678,11 +698,25 @@ bool make_coeff_plan(int64_t n, int nmax, int lmax, int prec, CoeffPlan* p) {
   if (q.nblocks > kCoeffThreads) return false;
   q.streams = kCoeffThreads / q.nblocks;
   if (q.streams > kMaxStreams) q.streams = kMaxStreams;
-  // particles per tile: one per lane of a wavefront, a multiple of the stream count
-  // (every stream takes the same number), within the LDS budget
+  // particles per tile: one per lane of a wavefront in each particle group (1, 2 or 4
+  // groups of 64, the four wavefronts splitting the basis jobs 4, 2 or 1 ways), a
+  // multiple of the stream count (every stream takes the same number), within the LDS
+  // budget; more groups when they fit (small cutoffs), so a tile does more work per
+  // barrier
   const size_t budget = esz == 4 ? 76 * 1024 : 150 * 1024;
   const size_t per_particle = size_t(q.spg + q.spz) * esz;
+  q.nw = 4;
   int tp = 64;
+  if (q.lb <= 6) {
+    for (int nw = 1; nw <= 2; nw *= 2) {
+      const int tmax = 64 * (4 / nw);
+      if (size_t(tmax) * per_particle <= budget && q.streams <= tmax) {
+        q.nw = nw;
+        tp = tmax;
+        break;
+      }
+    }
+  }
   if (size_t(tp) * per_particle > budget) tp = int(budget / per_particle);
   if (q.streams <= tp) tp = tp / q.streams * q.streams;
   if (tp < 1) return false;
@@ -691,7 +725,9 @@ bool make_coeff_plan(int64_t n, int nmax, int lmax, int prec, CoeffPlan* p) {
   const size_t merge_bytes = size_t(q.nblocks) * q.nb * q.bs * 8;
   if (merge_bytes > q.lds_bytes) q.lds_bytes = merge_bytes;
   if (q.lds_bytes > 160 * 1024) return false;
-  q.flush_tiles = 8;
+  // FP32 runs of about 72 particles per lane before each fold
+  const int per_tile = q.tp / q.streams > 0 ? q.tp / q.streams : 1;
+  q.flush_tiles = 72 / per_tile > 0 ? 72 / per_tile : 1;
   const int64_t ntiles = (n + q.tp - 1) / q.tp;
   const int wg_per_cu = (esz == 4 && q.lds_bytes <= 80 * 1024) ? 2 : 1;
   int64_t grid = int64_t(256) * wg_per_cu;
@@ -822,6 +858,7 @@ int launch_scf_coeffs_batched(const CoeffPlan& p, const double* x, const double*
   a.nblocks = p.nblocks;
   a.streams = p.streams;
   a.nchunks = p.nchunks;
+  a.flush_tiles = p.flush_tiles;
   const int wg_per_cu = (p.prec != ETICS_FP64 && p.lds_bytes <= 80 * 1024) ? 2 : 1;
   int grid = 256 * wg_per_cu;
   const int mu = max_units(ntotal, nsys);

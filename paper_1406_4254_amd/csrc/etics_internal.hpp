@@ -42,6 +42,7 @@ struct CoeffPlan {
   int nb, bs;             // register block: nb radial orders x bs angular slots
   int nchunks;            // radial chunks of nb orders
   int spg, spz;           // LDS strides (elements) per particle: radial rows, angular slots
+  int nw;                 // wavefronts sharing the basis jobs of a group of 64 particles
   int tp;                 // particles per tile
   int nblocks, streams;   // register blocks per stream, streams per workgroup
   int flush_tiles;        // FP32 run length (tiles) before folding into the wide accumulator
