@@ -519,10 +519,10 @@ struct ReduceArgs {
   double scale[(NCAP + 1) * (LCAP + 1)];  // -sqrt(4 pi) Atilde_nl k_n, index n*(lmax+1)+l
 };
 
-// Each workgroup sums 32 coefficient columns over all partials: 8 slices of rows
-// (slice s takes rows s, s+8, ...) are summed in row order, then the 8 slice sums
+// Each workgroup sums 8 coefficient columns over all partials: 32 slices of rows
+// (slice s takes rows s, s+32, ...) are summed in row order, then the 32 slice sums
 // are added in slice order.  The order is fixed, so the result is reproducible.
-constexpr int kRedCols = 32, kRedSlices = 8;
+constexpr int kRedCols = 8, kRedSlices = 32;
 
 template <int MODE>
 __global__ __launch_bounds__(256) void scf_reduce_kernel(const ReduceArgs a) {
