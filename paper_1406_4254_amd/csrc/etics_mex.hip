@@ -332,7 +332,8 @@ __global__ __launch_bounds__(kMexTile) void mex_tile_sums_kernel(const MexArgs<L
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* S = reinterpret_cast<double*>(lds_raw);  // [2(2l+1)][kMexTile]
   constexpr int NC = mex_nc(LB);
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: scalar addressing
   MexLane<T, LB> q;
   q.load(a, int64_t(blockIdx.x) * kMexTile + t);
   double rl = 1.0, rm = q.p.rinv;  // r^l, r^-(l+1)
@@ -435,7 +436,8 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* S = reinterpret_cast<double*>(lds_raw);  // [2(2l+1)][kMexTile]
   constexpr int NC = mex_nc(LB);
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: scalar addressing
   MexLane<T, LB> q;
   q.load(a, int64_t(blockIdx.x) * kMexTile + t);
   const MexParticle<T>& p = q.p;
@@ -447,6 +449,9 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
   static_for<LB + 1>([&](auto lc) {
     constexpr int l = decltype(lc)::value;
     if (l > a.lmax) return;
+    // one l at a time: nothing of a later l is computed early, so the live registers
+    // (and with them the occupancy) stay bounded
+    __builtin_amdgcn_sched_barrier(0);
     // Legendre row l+1 (for m Ybar / sin)
     mex_legendre_row<T, LB, l + 1>(q.Y, p.ct, p.st);
     constexpr int W = 2 * (2 * l + 1), H = 2 * l + 1;
@@ -458,8 +463,9 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
     // k: rows 126-2k, 127-2k, so the lanes before k hold the later particles).  The
     // tile's offset from the other tiles is added.  Columns are unrolled so that their
     // trees interleave.
-    static_for<(W + 1) / 2>([&](auto jc) {
-      const int c = 2 * decltype(jc)::value + wave;
+#pragma unroll 3
+    for (int j = 0; j < (W + 1) / 2; ++j) {
+      const int c = 2 * j + wave;
       if (c < W) {
         const bool fwd = c < H;
         double* cp = S + c * kMexTile + (fwd ? 2 * lane : kMexTile - 2 - 2 * lane);
@@ -472,12 +478,19 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
         *reinterpret_cast<double2*>(cp) =
             fwd ? make_double2(r_first, r_second) : make_double2(r_second, r_first);
       }
-    });
+    }
     __syncthreads();
-    // synthesis of this l from the particle's own q (components 0..2l) and p (2l+1..)
+    // synthesis of this l from the particle's own q (components 0..2l) and p (2l+1..).
+    // Radial factors of this l: inward q r^-(l+1), outward p r^l; d/dr; and (1/r) x
+    // factor.  At the origin rinv = 0 and rm = 0, so every inward factor is 0 there
+    // (no inward part) without a branch.
     {
       const double* row = S + t;
       const double g = 4.0 * kPi / (2.0 * l + 1.0);
+      const double fq = rm, fp = rl;                       // potential
+      const double dq = -(l + 1.0) * rm * p.rinv;          // d/dr r^-(l+1)
+      const double dp = double(l) * rlm1;                  // d/dr r^l
+      const double oq = rm * p.rinv, op = rlm1;            // (1/r) x radial factor
       static_for<l + 1>([&](auto mc) {
         constexpr int m = decltype(mc)::value;
         constexpr int sc = m == 0 ? 0 : 2 * m - 1;
@@ -486,22 +499,14 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
         const double qs = m > 0 ? row[(sc + 1) * kMexTile] : 0.0;
         const double ps = m > 0 ? row[(H + sc + 1) * kMexTile] : 0.0;
         const double c = double(q.cm[m]), s = double(q.sm[m]);
-        // radial factors: inward q r^-(l+1), outward p r^l; the inward part is absent
-        // for a particle at the origin
-        const double fq = p.at_origin ? 0.0 : rm;
-        const double e = (qc * c + qs * s) * fq + (pc * c + ps * s) * rl;
-        const double dr = p.at_origin ? (l >= 1 ? double(l) * rlm1 * (pc * c + ps * s) : 0.0)
-                                      : (-(l + 1.0) * rm * p.rinv * (qc * c + qs * s) +
-                                         double(l) * rlm1 * (pc * c + ps * s));
-        // (1/r) x radial factor: q r^-(l+2), p r^(l-1)
-        const double eo = p.at_origin ? (pc * c + ps * s) * rlm1
-                                      : (qc * c + qs * s) * rm * p.rinv + (pc * c + ps * s) * rlm1;
-        const double f = p.at_origin ? (ps * c - pc * s) * rlm1
-                                     : (qs * c - qc * s) * rm * p.rinv + (ps * c - pc * s) * rlm1;
-        const double y = double(q.Y[l][m]);
-        Phi -= w * y * e;
-        ar += w * y * dr;
+        const double Aq = qc * c + qs * s, Ap = pc * c + ps * s;  // cos-weighted parts
+        const double e = Aq * fq + Ap * fp;
+        const double dr = Aq * dq + Ap * dp;
+        const double wy = w * double(q.Y[l][m]);
+        Phi -= wy * e;
+        ar += wy * dr;
         if constexpr (l >= 1) {
+          const double eo = Aq * oq + Ap * op;
           T dY;
           if constexpr (m == 0) {
             dY = T(kTab.e1[l][0]) * q.Y[l][1];
@@ -512,6 +517,7 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
           }
           at += w * double(dY) * eo;
           if constexpr (m >= 1) {
+            const double f = (qs * c - qc * s) * oq + (ps * c - pc * s) * op;
             const T mYs = -(T(kTab.f1[l][m]) * q.Y[l + 1][m + 1] + T(kTab.f2[l][m]) * q.Y[l + 1][m - 1]);
             ap += w * double(mYs) * f;
           }
