@@ -222,27 +222,22 @@ struct MexArgs {
 constexpr int mex_nc(int lb) { return (lb + 1) * (lb + 1); }
 constexpr int mex_coff(int l) { return l * l; }  // first component of l (2l+1 per l)
 
-// Per l: each thread writes its 2(2l+1) summands to LDS, then every column is summed
-// (tile sums) or scanned (force).  The LDS block is column-major: component c of the
-// particle in row (sorted position within the tile) t is at col0[c * CS], col0 = S + t.
-template <typename T, int LB, int l, int CS>
+// Per l and side (0 = inward, 1 = outward): each thread writes its 2l+1 summands of that
+// side to LDS, then every column is summed (tile sums) or scanned (force).  The LDS block
+// is column-major: component c of the particle in row (sorted position within the tile)
+// t is at col0[c * CS], col0 = S + t.  Staging one side at a time halves the LDS of a
+// workgroup, so more workgroups share a CU.
+template <typename T, int LB, int l, int SIDE, int CS>
 __device__ __forceinline__ void mex_summands_col(const MexParticle<T>& p, const T (&Y)[LB + 2][LB + 2],
                                                  const T* cm, const T* sm, double rl, double rm,
                                                  bool valid, double* col0) {
-  // components 0 .. 2l: inward (m r^l Ybar trig); 2l+1 .. 4l+1: outward (m r^-(l+1) Ybar trig)
-  const double wi = valid ? p.mass * rl : 0.0;
-  const double wo = (valid && !p.at_origin) ? p.mass * rm : 0.0;
+  // inward: m r^l Ybar trig; outward: m r^-(l+1) Ybar trig (0 at the origin, rm = 0)
+  const double wgt = valid ? p.mass * (SIDE == 0 ? rl : rm) : 0.0;
   static_for<l + 1>([&](auto mc) {
     constexpr int m = decltype(mc)::value;
     constexpr int sc = m == 0 ? 0 : 2 * m - 1;
-    const double yc = double(Y[l][m] * cm[m]);
-    col0[sc * CS] = wi * yc;
-    col0[(2 * l + 1 + sc) * CS] = wo * yc;
-    if constexpr (m > 0) {
-      const double ys = double(Y[l][m] * sm[m]);
-      col0[(sc + 1) * CS] = wi * ys;
-      col0[(2 * l + 1 + sc + 1) * CS] = wo * ys;
-    }
+    col0[sc * CS] = wgt * double(Y[l][m] * cm[m]);
+    if constexpr (m > 0) col0[(sc + 1) * CS] = wgt * double(Y[l][m] * sm[m]);
   });
 }
 
@@ -330,7 +325,7 @@ struct MexLane {
 template <typename T, int LB>
 __global__ __launch_bounds__(kMexTile) void mex_tile_sums_kernel(const MexArgs<LB> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* S = reinterpret_cast<double*>(lds_raw);  // [2(2l+1)][kMexTile]
+  double* S = reinterpret_cast<double*>(lds_raw);  // [2l+1][kMexTile], one side at a time
   constexpr int NC = mex_nc(LB);
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: scalar addressing
@@ -342,20 +337,23 @@ __global__ __launch_bounds__(kMexTile) void mex_tile_sums_kernel(const MexArgs<L
     constexpr int l = decltype(lc)::value;
     if (l > a.lmax) return;
     if constexpr (l >= 1) mex_legendre_row<T, LB, l>(q.Y, q.p.ct, q.p.st);
-    constexpr int W = 2 * (2 * l + 1), H = 2 * l + 1;
-    mex_summands_col<T, LB, l, kMexTile>(q.p, q.Y, q.cm, q.sm, rl, rm, q.valid, S + t);
-    __syncthreads();
-    // one wavefront per column: two rows per lane, then a lane tree; the columns of a
-    // wavefront are independent and unrolled so their trees interleave
-    static_for<(W + 1) / 2>([&](auto jc) {
-      const int c = 2 * decltype(jc)::value + wave;
-      if (c < W) {
-        const double2 v = *reinterpret_cast<const double2*>(S + c * kMexTile + 2 * lane);
-        const double tot = wave_sum(v.x + v.y);
-        if (lane == 0) out[(c < H ? 0 : NC) + mex_coff(l) + (c < H ? c : c - H)] = tot;
-      }
+    constexpr int H = 2 * l + 1;
+    static_for<2>([&](auto sidec) {
+      constexpr int side = decltype(sidec)::value;
+      mex_summands_col<T, LB, l, side, kMexTile>(q.p, q.Y, q.cm, q.sm, rl, rm, q.valid, S + t);
+      __syncthreads();
+      // one wavefront per column: two rows per lane, then a lane tree; the columns of a
+      // wavefront are independent and unrolled so their trees interleave
+      static_for<(H + 1) / 2>([&](auto jc) {
+        const int c = 2 * decltype(jc)::value + wave;
+        if (c < H) {
+          const double2 v = *reinterpret_cast<const double2*>(S + c * kMexTile + 2 * lane);
+          const double tot = wave_sum(v.x + v.y);
+          if (lane == 0) out[side * NC + mex_coff(l) + c] = tot;
+        }
+      });
+      __syncthreads();
     });
-    __syncthreads();
     rl *= q.p.r;
     rm *= q.p.rinv;
   });
@@ -434,7 +432,7 @@ __global__ __launch_bounds__(256) void mex_tile_offsets_kernel(const MexArgs<LB>
 template <typename T, int LB>
 __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* S = reinterpret_cast<double*>(lds_raw);  // [2(2l+1)][kMexTile]
+  double* S = reinterpret_cast<double*>(lds_raw);  // [2l+1][kMexTile], one side at a time
   constexpr int NC = mex_nc(LB);
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: scalar addressing
@@ -454,33 +452,42 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
     __builtin_amdgcn_sched_barrier(0);
     // Legendre row l+1 (for m Ybar / sin)
     mex_legendre_row<T, LB, l + 1>(q.Y, p.ct, p.st);
-    constexpr int W = 2 * (2 * l + 1), H = 2 * l + 1;
-    mex_summands_col<T, LB, l, kMexTile>(p, q.Y, q.cm, q.sm, rl, rm, q.valid, S + t);
-    __syncthreads();
-    // exclusive scans of every column inside the tile, one wavefront per column: lane k
-    // takes two consecutive rows, then a lane tree gives what the lanes before it hold.
-    // Inward columns run forward (lane k: rows 2k, 2k+1); outward columns backward (lane
-    // k: rows 126-2k, 127-2k, so the lanes before k hold the later particles).  The
-    // tile's offset from the other tiles is added.  Columns are unrolled so that their
-    // trees interleave.
+    constexpr int H = 2 * l + 1;
+    // exclusive scans of every column inside the tile, one side at a time, one
+    // wavefront per column: lane k takes two consecutive rows, then a lane tree gives
+    // what the lanes before it hold.  Inward columns run forward (lane k: rows 2k, 2k+1);
+    // outward columns backward (lane k: rows 126-2k, 127-2k, so the lanes before k hold
+    // the later particles).  The tile's offset from the other tiles is added.  The
+    // particle keeps its own inward values in registers while the outward side reuses
+    // the LDS block.
+    double qv[H];
+    static_for<2>([&](auto sidec) {
+      constexpr int side = decltype(sidec)::value;
+      mex_summands_col<T, LB, l, side, kMexTile>(p, q.Y, q.cm, q.sm, rl, rm, q.valid, S + t);
+      __syncthreads();
 #pragma unroll 3
-    for (int j = 0; j < (W + 1) / 2; ++j) {
-      const int c = 2 * j + wave;
-      if (c < W) {
-        const bool fwd = c < H;
-        double* cp = S + c * kMexTile + (fwd ? 2 * lane : kMexTile - 2 - 2 * lane);
-        const double2 v = *reinterpret_cast<const double2*>(cp);
-        const double off = offs[(fwd ? 0 : NC) + mex_coff(l) + (fwd ? c : c - H)];
-        // within the pair: the first row in scan order gets 0, the second the first
-        const double first = fwd ? v.x : v.y, second = fwd ? v.y : v.x;
-        const double base = off + wave_excl_prefix(first + second);
-        const double r_first = base, r_second = base + first;
-        *reinterpret_cast<double2*>(cp) =
-            fwd ? make_double2(r_first, r_second) : make_double2(r_second, r_first);
+      for (int j = 0; j < (H + 1) / 2; ++j) {
+        const int c = 2 * j + wave;
+        if (c < H) {
+          double* cp = S + c * kMexTile + (side == 0 ? 2 * lane : kMexTile - 2 - 2 * lane);
+          const double2 v = *reinterpret_cast<const double2*>(cp);
+          const double off = offs[side * NC + mex_coff(l) + c];
+          // within the pair: the first row in scan order gets 0, the second the first
+          const double first = side == 0 ? v.x : v.y, second = side == 0 ? v.y : v.x;
+          const double base = off + wave_excl_prefix(first + second);
+          const double r_first = base, r_second = base + first;
+          *reinterpret_cast<double2*>(cp) =
+              side == 0 ? make_double2(r_first, r_second) : make_double2(r_second, r_first);
+        }
       }
-    }
-    __syncthreads();
-    // synthesis of this l from the particle's own q (components 0..2l) and p (2l+1..).
+      __syncthreads();
+      if constexpr (side == 0) {
+#pragma unroll
+        for (int c = 0; c < H; ++c) qv[c] = S[c * kMexTile + t];
+        __syncthreads();  // every lane has its inward values before the outward side
+      }
+    });
+    // synthesis of this l from the particle's own q (registers) and p (LDS).
     // Radial factors of this l: inward q r^-(l+1), outward p r^l; d/dr; and (1/r) x
     // factor.  At the origin rinv = 0 and rm = 0, so every inward factor is 0 there
     // (no inward part) without a branch.
@@ -495,9 +502,9 @@ __global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a
         constexpr int m = decltype(mc)::value;
         constexpr int sc = m == 0 ? 0 : 2 * m - 1;
         const double w = (m == 0 ? 1.0 : 2.0) * g;
-        const double qc = row[sc * kMexTile], pc = row[(H + sc) * kMexTile];
-        const double qs = m > 0 ? row[(sc + 1) * kMexTile] : 0.0;
-        const double ps = m > 0 ? row[(H + sc + 1) * kMexTile] : 0.0;
+        const double qc = qv[sc], pc = row[sc * kMexTile];
+        const double qs = m > 0 ? qv[sc + 1] : 0.0;
+        const double ps = m > 0 ? row[(sc + 1) * kMexTile] : 0.0;
         const double c = double(q.cm[m]), s = double(q.sm[m]);
         const double Aq = qc * c + qs * s, Ap = pc * c + ps * s;  // cos-weighted parts
         const double e = Aq * fq + Ap * fp;
@@ -580,8 +587,8 @@ MexLayout mex_layout(int64_t n, int lmax) {
 
 template <typename T, int LB>
 int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
-  // largest LDS block: 2(2l+1) columns of kMexTile doubles at l = LB
-  const size_t lds = size_t(kMexTile) * (2 * (2 * LB + 1)) * 8;
+  // largest LDS block: 2l+1 columns (one side) of kMexTile doubles at l = LB
+  const size_t lds = size_t(kMexTile) * (2 * LB + 1) * 8;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(mex_tile_sums_kernel<T, LB>),
