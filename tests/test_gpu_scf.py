@@ -101,6 +101,23 @@ def test_mixed_force_accuracy(E, orc, prec, cfg, n, nmax, lmax):
     assert ce["norm_rel"] < 1e-5
 
 
+@pytest.mark.parametrize("prec", [MIXED, COMP32])
+@pytest.mark.parametrize("nmax,lmax", [(0, 0), (3, 1), (6, 2), (8, 6), (12, 6)])
+def test_mixed_small_cutoffs_ragged(E, orc, prec, nmax, lmax):
+    """Small cutoffs use tiles of 128 or 256 particles; a ragged N (not a multiple of
+    the tile) must still reach the gate."""
+    p = W.make_config(2, 5003)
+    A, B = gpu_coeffs(E, p, nmax, lmax, prec)
+    rA, rB = orc.scf_coeffs(p.x, p.y, p.z, p.m, nmax, lmax)
+    assert acc.coeff_errors(A, B, rA, rB)["norm_rel"] < 1e-5
+    pot, ax, ay, az = gpu_force(E, p, nmax, lmax, A, B, prec)
+    rp, rx, ry, rz = orc.scf_force(p.x, p.y, p.z, nmax, lmax, rA, rB)
+    ef = report(f"small ({nmax},{lmax}) prec{prec} force", acc.force_rel_err(ax, ay, az, rx, ry, rz))
+    ep = report(f"small ({nmax},{lmax}) prec{prec} pot", acc.pot_rel_err(pot, rp))
+    assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4
+    assert ep["median"] <= 1e-5 and ep["p99"] <= 1e-4
+
+
 def test_cfg2_full_size(E, orc):
     """N = 10^6, (10,10), triaxial Hernquist: the benchmark workload, every particle."""
     p = W.make_config(2)
