@@ -196,9 +196,25 @@ def main():
             "wall_s": wall,
             "coeff_call_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
             "force_call_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in evs])),
+            "step_ms_sd": float(np.std([e[0].elapsed_time(e[2]) for e in evs])),
             "coeff_kernel_ms": kc.mean_ms(),
             "force_kernel_ms": kf.mean_ms(),
         }
+        # the same step captured once into a graph and replayed (the calls allocate and
+        # synchronise nothing, so they can be captured)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            etics.etics_scf_coeffs(x, y, z, m, nmax, lmax, prec, A, B, ws)
+            etics.etics_scf_force(x, y, z, nmax, lmax, A, B, prec, etics.ETICS_POT_ACC, pot, ax, ay, az, ws)
+        g.replay()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res["graph_ms_per_step"] = e0.elapsed_time(e1) / steps
         out = [t.cpu().numpy() for t in (A, B, pot, ax, ay, az)]
         return res, out
 

@@ -245,13 +245,15 @@ def etics_scf_force_batched(x, y, z, offsets, nmax: int, lmax: int, A, B, precis
     _dev(offsets, "offsets", torch.int64)
     nsys = offsets.numel() - 1
     n = x.numel()
+    for t, nm in ((x, "x"), (y, "y"), (z, "z"), (A, "A"), (B, "B")):
+        _dev(t, nm)
     mk = lambda: torch.empty(n, dtype=torch.float64, device=x.device)
     if outputs & ETICS_POT:
-        pot = mk() if pot is None else pot
+        pot = mk() if pot is None else _dev(pot, "pot")
     if outputs & ETICS_ACC:
-        ax = mk() if ax is None else ax
-        ay = mk() if ay is None else ay
-        az = mk() if az is None else az
+        ax = mk() if ax is None else _dev(ax, "ax")
+        ay = mk() if ay is None else _dev(ay, "ay")
+        az = mk() if az is None else _dev(az, "az")
     need = etics_batched_workspace_size(n, nsys, nmax, lmax, p)
     ws = workspace(need, x.device) if ws is None else ws
     _check(lib().etics_scf_force_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(offsets), nsys, n, nmax, lmax,

@@ -233,3 +233,41 @@ def test_cfg3_full_size_sampled(E, orc):
         else:
             assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4 and ep["median"] <= 1e-5 and ep["p99"] <= 1e-4
         del pot, ax, ay, az
+
+
+def test_graph_capture_replays_match_eager(E):
+    """etics_scf_coeffs + etics_scf_force captured into a graph (they allocate and
+    synchronise nothing): every replay, with eager calls and synchronisations between
+    the replays, gives the eager result bit for bit."""
+    import torch
+    p = W.make_config(2, 20_000)
+    x, y, z, m = dev(p.x, p.y, p.z, p.m)
+    nmax, lmax, n = 10, 10, p.x.shape[0]
+    for prec in (MIXED, FP64):
+        K = E.etics_coeff_count(nmax, lmax)
+        ws = E.workspace(E.etics_scf_workspace_size(n, nmax, lmax, prec), "cuda")
+        A, B = (torch.empty(K, dtype=torch.float64, device="cuda") for _ in range(2))
+        outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+
+        def step():
+            E.etics_scf_coeffs(x, y, z, m, nmax, lmax, prec, A, B, ws)
+            E.etics_scf_force(x, y, z, nmax, lmax, A, B, prec, E.ETICS_POT_ACC, *outs, ws)
+
+        step()  # eager reference (also sets the kernels' launch attributes before capture)
+        torch.cuda.synchronize()
+        ref = [t.clone() for t in [A, B, *outs]]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for k in range(3):
+            for t in [A, B, *outs]:
+                t.fill_(float("nan"))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for got, want in zip([A, B, *outs], ref):
+                assert torch.equal(got, want), f"replay {k} differs (prec {prec})"
+            step()  # eager work between replays
+            torch.cuda.synchronize()
+            for got, want in zip([A, B, *outs], ref):
+                assert torch.equal(got, want)
