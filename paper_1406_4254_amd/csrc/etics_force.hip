@@ -121,18 +121,20 @@ __device__ __forceinline__ void force_point(const ForceArgs& a, const T* __restr
         legendre_row(std::integral_constant<int, l>{});
       }
 
-      // radial sums over n: U,V (potential), W,X (radial derivative)
+      // radial sums over n: U,V (potential), W,X (radial derivative).  Order 0 is taken
+      // in closed form (Chat_0 = 1; it adds nothing to W, X since Ehat_{-1} = 0), the
+      // loop starts at order 1.
+      const T* cfl = cf + l * (l + 1) / 2;
       T U[l + 1], V[l + 1], W[l + 1], X[l + 1];
 #pragma unroll
       for (int m = 0; m <= l; ++m) {
-        U[m] = T(0);
-        V[m] = T(0);
+        U[m] = cfl[m];
+        V[m] = m > 0 ? cfl[K + m] : T(0);
         W[m] = T(0);
         X[m] = T(0);
       }
-      T c2 = T(1), c1 = T(0);  // Chat_{n-2}, Chat_{n-1}
-      T e2 = T(1), e1 = T(0);  // Ehat_{n-2}, Ehat_{n-1} (parameter a_l + 1)
-      const T* cfl = cf + l * (l + 1) / 2;
+      T c2 = T(0), c1 = T(1);  // Chat_{n-2}, Chat_{n-1} for n = 1 (Chat_{-1} enters times 0)
+      T e2 = T(0), e1 = T(1);  // Ehat_{n-2}, Ehat_{n-1} (parameter a_l + 1)
       const T* ql = tb.q[l];
       const T* qdl = tb.qd[l];
       // one radial order: c <- Chat_nn, accumulate, advance Ehat
@@ -157,7 +159,7 @@ __device__ __forceinline__ void force_point(const ForceArgs& a, const T* __restr
       };
       if constexpr (sizeof(T) == 4) {
         // two orders per trip: the recurrence registers swap roles instead of moving
-        int nn = 0;
+        int nn = 1;
         for (; nn + 1 <= nmax; nn += 2) {
           step(nn, c2, c1, e2, e1);      // c2 <- Chat_nn, e2 <- Ehat_nn
           step(nn + 1, c1, c2, e1, e2);  // c1 <- Chat_{nn+1}, e1 <- Ehat_{nn+1}
@@ -165,7 +167,7 @@ __device__ __forceinline__ void force_point(const ForceArgs& a, const T* __restr
         if (nn <= nmax) step(nn, c2, c1, e2, e1);
       } else {
         // FP64 coefficients take two SGPRs each: one order per trip keeps them in SGPRs
-        for (int nn = 0; nn <= nmax; ++nn) {
+        for (int nn = 1; nn <= nmax; ++nn) {
           step(nn, c2, c1, e2, e1);
           const T tc = c2, te = e2;
           c2 = c1;
