@@ -40,10 +40,16 @@ struct CoeffArgs {
 };
 
 // ------------------------------------------------------------ phase-1 job plan
-// Greedy longest-job-first split of the basis jobs of a cutoff bucket between the NW
-// wavefronts that share a group of 64 particles (NW = 4: the whole workgroup; NW = 2 or
-// 1: two or four groups, so a tile holds 128 or 256 particles).  Angular job m costs ~6
-// operations per l in [m, lb]; radial job l ~2 operations per padded radial order.
+// The basis jobs of a cutoff bucket are split between the NW wavefronts that share a
+// group of 64 particles (NW = 4: the whole workgroup; NW = 2 or 1: two or four groups,
+// so a tile holds 128 or 256 particles).  Angular job m (the Legendre column of m times
+// (cos, sin)(m phi)) costs ~6 operations per l in [m, lb]; before it, a wavefront walks
+// the diagonal from m = 0 up to the largest column it owns (~6 operations per step), so
+// each wavefront gets a contiguous range of columns and the low columns go together.
+// Radial job l (a Gegenbauer row) costs ~2 operations per padded order; a wavefront
+// with radial jobs only needs xi alone, not the angles.  The plan is the contiguous
+// split (searched over all cut points) with the smallest max + total/4 load, radial
+// jobs added greedily to the least loaded wavefront.
 template <int LB, int NRP, int NW>
 struct JobPlan {
   int ownerZ[LB + 1];
@@ -53,42 +59,57 @@ struct JobPlan {
 
 template <int LB, int NRP, int NW>
 constexpr JobPlan<LB, NRP, NW> make_job_plan() {
-  JobPlan<LB, NRP, NW> p{};
-  int code[2 * (LB + 1)] = {};
-  int cost[2 * (LB + 1)] = {};
-  int nj = 0;
-  for (int m = 0; m <= LB; ++m) {
-    code[nj] = m;
-    cost[nj++] = 6 * (LB - m + 1) + 8;
-  }
-  for (int l = 0; l <= LB; ++l) {
-    code[nj] = 0x80 | l;
-    cost[nj++] = 2 * NRP + NRP / 4 + 2;
-  }
-  for (int i = 1; i < nj; ++i)
-    for (int j = i; j > 0 && cost[j] > cost[j - 1]; --j) {
-      int c = cost[j];
-      cost[j] = cost[j - 1];
-      cost[j - 1] = c;
-      c = code[j];
-      code[j] = code[j - 1];
-      code[j - 1] = c;
+  constexpr int kDiag = 6, kSphSave = 25;
+  constexpr int kRad = 2 * NRP + NRP / 4 + 2;
+  auto zcost = [](int m) { return 6 * (LB - m + 1) + 8; };
+  JobPlan<LB, NRP, NW> best{};
+  long best_key = -1;
+  // k = number of wavefronts with angular columns; cut[i] = first column of range i+1
+  for (int k = 1; k <= NW && k <= LB + 1; ++k) {
+    int cut[NW + 1] = {};
+    for (int i = 0; i < k - 1; ++i) cut[i] = i + 1;  // first combination of k-1 cuts
+    while (true) {
+      JobPlan<LB, NRP, NW> p{};
+      int load[NW] = {};
+      for (int w = 0; w < NW; ++w) p.maxm[w] = -1;
+      int lo = 0;
+      for (int r = 0; r < k; ++r) {
+        const int hi = (r < k - 1 ? cut[r] : LB + 1) - 1;
+        for (int m = lo; m <= hi; ++m) {
+          p.ownerZ[m] = r;
+          load[r] += zcost(m);
+        }
+        load[r] += kDiag * hi;
+        p.maxm[r] = hi;
+        lo = hi + 1;
+      }
+      for (int w = k; w < NW; ++w) load[w] = -kSphSave;
+      for (int l = 0; l <= LB; ++l) {
+        int w = 0;
+        for (int q = 1; q < NW; ++q)
+          if (load[q] < load[w]) w = q;
+        p.ownerG[l] = w;
+        load[w] += kRad;
+      }
+      long mx = load[0], tot = 0;
+      for (int w = 0; w < NW; ++w) {
+        tot += load[w];
+        if (load[w] > mx) mx = load[w];
+      }
+      const long key = 4 * mx + tot;
+      if (best_key < 0 || key < best_key) {
+        best_key = key;
+        best = p;
+      }
+      // next combination of k-1 cut points from 1..LB (increasing)
+      int i = k - 2;
+      while (i >= 0 && cut[i] == LB - (k - 2 - i)) --i;
+      if (i < 0) break;
+      ++cut[i];
+      for (int j = i + 1; j < k - 1; ++j) cut[j] = cut[j - 1] + 1;
     }
-  int load[NW] = {};
-  for (int w = 0; w < NW; ++w) p.maxm[w] = -1;
-  for (int i = 0; i < nj; ++i) {
-    int w = 0;
-    for (int k = 1; k < NW; ++k)
-      if (load[k] < load[w]) w = k;
-    load[w] += cost[i];
-    if (code[i] & 0x80) {
-      p.ownerG[code[i] & 0x7f] = w;
-    } else {
-      p.ownerZ[code[i]] = w;
-      if (code[i] > p.maxm[w]) p.maxm[w] = code[i];
-    }
   }
-  return p;
+  return best;
 }
 
 // wide accumulator: MODE 0 -> FP64; MODE 1 -> compensated FP32 pair (hi, lo)
@@ -246,15 +267,29 @@ struct CoeffWG {
 
   // phase 1: basis of the particle of this lane (zero mass for an empty lane)
   __device__ __forceinline__ void phase1(double xd, double yd, double zd, double md) {
-    constexpr JobPlan<LB, NRP, NW> kJP = make_job_plan<LB, NRP, NW>();
     if (pidx >= tp) return;
-    const Sph<T> s = sph<T>(xd, yd, zd);
-    const T tu = s.t * s.u, ctu = s.ct * tu, tu2 = tu * tu, stu = s.st * tu;
     T* Gp = G + pidx * SPG;
     T* Zp = Z + pidx * SPZ;
-    // angular jobs: column m of mass u (tu)^l Ybar_lm (cos, sin)(m phi), l = m..lmax.
-    // The diagonal value mass u (tu)^m Ybar_mm and (cos, sin)(m phi) are walked up to
-    // the largest column this wavefront owns.
+    T xi;
+    if (maxm_w >= 0) {
+      const Sph<T> s = sph<T>(xd, yd, zd);
+      xi = s.xi;
+      angular_jobs(s, md, Zp);
+    } else {  // radial jobs only: xi = (r - 1) / (r + 1) alone
+      const T x = T(xd), y = T(yd), z = T(zd);
+      const T r = sqrt_(x * x + y * y + z * z);
+      const T u = rcp_(T(1) + r);
+      xi = r * u - u;
+    }
+    radial_jobs(xi, Gp);
+  }
+
+  // angular jobs: column m of mass u (tu)^l Ybar_lm (cos, sin)(m phi), l = m..lmax.  The
+  // diagonal value mass u (tu)^m Ybar_mm and (cos, sin)(m phi) are walked up to the
+  // largest column this wavefront owns.
+  __device__ __forceinline__ void angular_jobs(const Sph<T>& s, double md, T* Zp) {
+    constexpr JobPlan<LB, NRP, NW> kJP = make_job_plan<LB, NRP, NW>();
+    const T tu = s.t * s.u, ctu = s.ct * tu, tu2 = tu * tu, stu = s.st * tu;
     T Pd = T(md) * s.u * T(kTab.c1[0][0]);
     T cmc = T(1), smc = T(0);
     static_for<LB + 1>([&](auto mc) {
@@ -289,8 +324,12 @@ struct CoeffWG {
         });
       }
     });
-    // radial jobs: monic Gegenbauer Chat_n^(2l+3/2)(xi), n = 0..NRP-1.  Entries past
-    // nmax only feed coefficients that are never written out; they stay finite.
+  }
+
+  // radial jobs: monic Gegenbauer Chat_n^(2l+3/2)(xi), n = 0..NRP-1.  Entries past nmax
+  // only feed coefficients that are never written out; they stay finite.
+  __device__ __forceinline__ void radial_jobs(T xi, T* Gp) {
+    constexpr JobPlan<LB, NRP, NW> kJP = make_job_plan<LB, NRP, NW>();
     static_for<LB + 1>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
       if (rank == kJP.ownerG[l] && l <= lmax) {
@@ -300,7 +339,7 @@ struct CoeffWG {
           T v[4];
           static_for<4>([&](auto jc) {
             constexpr int nn = nb4 + decltype(jc)::value;
-            const T c = s.xi * p1 - T(kTab.q[l][nn]) * p2;
+            const T c = xi * p1 - T(kTab.q[l][nn]) * p2;
             p2 = p1;
             p1 = c;
             v[decltype(jc)::value] = c;
