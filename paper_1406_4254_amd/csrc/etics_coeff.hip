@@ -383,17 +383,22 @@ struct CoeffWG {
           gv[buf][2 * q + 1] = f.y;
         }
       }
-      static_assert(BS % 2 == 0, "angular blocks are read in aligned pairs");
+      static_assert(BS % 4 == 0, "angular blocks are read in aligned 4-slot groups");
 #pragma unroll
-      for (int j = 0; j < BS; j += 2) {
+      for (int j = 0; j < BS; j += 4) {
         if constexpr (sizeof(T) == 4) {
-          const float2 f = reinterpret_cast<const float2*>(zz)[j / 2];
+          const float4 f = reinterpret_cast<const float4*>(zz)[j / 4];
           zv[buf][j] = f.x;
           zv[buf][j + 1] = f.y;
+          zv[buf][j + 2] = f.z;
+          zv[buf][j + 3] = f.w;
         } else {
-          const double2 f = reinterpret_cast<const double2*>(zz)[j / 2];
-          zv[buf][j] = f.x;
-          zv[buf][j + 1] = f.y;
+          const double2 f0 = reinterpret_cast<const double2*>(zz)[j / 2];
+          const double2 f1 = reinterpret_cast<const double2*>(zz)[j / 2 + 1];
+          zv[buf][j] = f0.x;
+          zv[buf][j + 1] = f0.y;
+          zv[buf][j + 2] = f1.x;
+          zv[buf][j + 3] = f1.y;
         }
       }
     };
