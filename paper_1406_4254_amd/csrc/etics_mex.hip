@@ -430,7 +430,7 @@ __global__ __launch_bounds__(256) void mex_tile_offsets_kernel(const MexArgs<LB>
 
 // per-particle synthesis
 template <typename T, int LB>
-__global__ __launch_bounds__(kMexTile) void mex_force_kernel(const MexArgs<LB> a) {
+__global__ __launch_bounds__(kMexTile, LB <= 10 ? 3 : 2) void mex_force_kernel(const MexArgs<LB> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* S = reinterpret_cast<double*>(lds_raw);  // [2l+1][kMexTile], one side at a time
   constexpr int NC = mex_nc(LB);
