@@ -229,12 +229,17 @@ def main():
                 **{k: v for k, v in r64.items() if k != "wall_s"}}
 
     fc, ff = flops_per_particle(nmax, lmax)
+    # kernel names as the profiler prints them (template arguments: compute type, lmax
+    # bucket, radial orders per register block, angular slots per block, accumulation
+    # mode, wavefronts per particle group)
     lb_force = 2 if lmax <= 2 else (lmax + 1) // 2 * 2
     lb_coeff = 2 if lmax <= 2 else (6 if lmax <= 6 else (10 if lmax <= 10 else 14))
     nb = 9 if nmax + 1 <= 9 else (11 if nmax + 1 <= 11 else 12)
+    coeff_name = (f"scf_coeff_kernel<float, {lb_coeff}, {nb}, 4, 0, 4>" if lb_coeff >= 10
+                  else f"scf_coeff_kernel<float, {lb_coeff}, {nb}, 4, 0, nw>")
     kernels = {
-        "force": (mixed["force_kernel_ms"], ff, f"scf_force_kernel<float,{lb_force},true>"),
-        "coeff": (mixed["coeff_kernel_ms"], fc, f"scf_coeff_kernel<float,{lb_coeff},{nb},4,0>"),
+        "force": (mixed["force_kernel_ms"], ff, f"scf_force_kernel<float, {lb_force}, true>"),
+        "coeff": (mixed["coeff_kernel_ms"], fc, coeff_name),
     }
     dom = max(kernels, key=lambda k: kernels[k][0])
     dom_ms, dom_fpp, dom_name = kernels[dom]

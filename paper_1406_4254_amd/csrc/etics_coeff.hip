@@ -24,6 +24,7 @@
 //   depend on how the hardware schedules workgroups.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 
@@ -655,12 +656,16 @@ int launch_coeff_t(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) 
     kfn = reinterpret_cast<const void*>(scf_coeff_batched_kernel<T, LB, NB, BS, MODE, NW>);
   else
     kfn = reinterpret_cast<const void*>(scf_coeff_kernel<T, LB, NB, BS, MODE, NW>);
-  static bool attr_set = false;
-  if (!attr_set) {
-    // the kernel has no static LDS: the whole 160 KiB of a CU may be requested
+  // the kernel has no static LDS: the whole 160 KiB of a CU may be requested (once per
+  // device and kernel)
+  static std::atomic<uint64_t> attr_done{0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const uint64_t bit = dev < 64 ? (uint64_t(1) << dev) : 0;
+  if (!bit || !(attr_done.load(std::memory_order_acquire) & bit)) {
     hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(scf_coeff)");
-    attr_set = true;
+    attr_done.fetch_or(bit, std::memory_order_acq_rel);
   }
   int rc = hook_before(st);
   if (rc) return rc;

@@ -589,16 +589,7 @@ template <typename T, int LB>
 int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
   // largest LDS block: 2l+1 columns (one side) of kMexTile doubles at l = LB
   const size_t lds = size_t(kMexTile) * (2 * LB + 1) * 8;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(mex_tile_sums_kernel<T, LB>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(mex_force_kernel<T, LB>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(mex)");
-    attr_set = true;
-  }
+  // at most 2l+1 <= 29 columns of 128 doubles (29.7 KiB): within the default LDS limit
   hipLaunchKernelGGL((mex_tile_sums_kernel<T, LB>), dim3(ntiles), dim3(kMexTile), lds, st, a);
   int rc = hip_fail(hipGetLastError(), "mex_tile_sums_kernel launch");
   if (rc) return rc;
