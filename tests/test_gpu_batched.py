@@ -165,3 +165,18 @@ def test_cfg5_full_size_sampled(E, orc):
         ef = acc.summarize(acc.force_rel_err(ax[b:e].cpu().numpy(), ay[b:e].cpu().numpy(),
                                              az[b:e].cpu().numpy(), rx, ry, rz))
         assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4, (s, ef)
+
+
+def test_leapfrog_step_counts_and_cache_replacement(E, orc):
+    """nsteps = 0 changes nothing; nsteps = 1 (no graph) and several graph calls with
+    different step counts and dt (the cached graph is replaced) all match the oracle."""
+    p = small_batch(nsys=3, seed=38, nlog=(2.5, 3.0))
+    nmax, lmax = 6, 4
+    same = run_lf(E, p, nmax, lmax, 0.01, 0, FP64)
+    for a, b in zip(same, (p.x, p.y, p.z, p.vx, p.vy, p.vz)):
+        assert np.array_equal(a, b)
+    for dt, steps in ((0.01, 1), (0.02, 3), (0.01, 5)):
+        got = run_lf(E, p, nmax, lmax, dt, steps, FP64)
+        ref = orc.leapfrog_scf(p.x, p.y, p.z, p.vx, p.vy, p.vz, p.m, p.offsets, nmax, lmax, dt, steps)
+        for g, r in zip(got, ref):
+            np.testing.assert_allclose(g, r, rtol=1e-9, atol=1e-11)
