@@ -332,8 +332,14 @@ def extras(torch, np, etics, workloads, stream, reps=10):
         etics.etics_set_timing_events(None, None)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
+        # algorithmic bytes: x, y, z, m in and pot, a out (64 B) plus 8 radix passes over
+        # an 8-byte key and a 4-byte index, read and written (8 x 24 B)
+        mex_bytes = n * (64 + 8 * 24)
         ex[f"mex_{name}"] = {"workload": "mex_plummer_hernquist_n1e6_l10", "ms_per_call": ms,
-                             "particles_per_s": n / (ms * 1e-3), "synthesis_kernel_ms": kt.mean_ms()}
+                             "particles_per_s": n / (ms * 1e-3), "synthesis_kernel_ms": kt.mean_ms(),
+                             "algorithmic_bytes": mex_bytes,
+                             "achieved_GBs": mex_bytes / (ms * 1e-3) / 1e9,
+                             "frac_of_hbm_peak": mex_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
     del x, y, z, m
     q = workloads.make_config(5)
     nt = q.x.shape[0]
@@ -351,9 +357,12 @@ def extras(torch, np, etics, workloads, stream, reps=10):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     # one call = one extra force calculation at the start + nsteps graph replays
+    fc, ff = flops_per_particle(8, 6)
+    step_ms = ms / (nsteps + 1)
     ex["leapfrog_batched_mixed"] = {"workload": "batched_256_spheres_n8_l6", "particles": nt, "nsteps": nsteps,
-                                    "ms_per_call": ms, "ms_per_step": ms / (nsteps + 1),
-                                    "particle_steps_per_s": nt * (nsteps + 1) / (ms * 1e-3)}
+                                    "ms_per_call": ms, "ms_per_step": step_ms,
+                                    "particle_steps_per_s": nt * (nsteps + 1) / (ms * 1e-3),
+                                    "step_tflops": (fc + ff) * nt / (step_ms * 1e-3) / 1e12}
     return ex
 
 
