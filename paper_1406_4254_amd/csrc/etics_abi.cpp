@@ -1,6 +1,7 @@
 // etics_abi.cpp -- the C-ABI entry points of libetics.so: argument validation,
-// workspace sizing and dispatch to the HIP kernels.  No entry point allocates,
-// synchronises or copies to/from the host.
+// workspace sizing and dispatch to the HIP kernels.  No entry point allocates device
+// memory, synchronises or copies to/from the host; the leapfrog alone creates a
+// library stream and instantiates a graph on its first use.
 #include <hip/hip_runtime.h>
 
 #include <climits>

@@ -4,13 +4,15 @@
 // particles k of m_k PhiT_nl(r_k) Ybar_lm(theta_k) (cos, sin)(m phi_k) for every
 // (n, l, m) (eq. scf-phi with the Hernquist-Ostriker basis of Section 2.5).
 //
-// scf_coeff_kernel: each workgroup (4 wavefronts) walks tiles of `tp` particles.
+// scf_coeff_kernel: each workgroup (4 wavefronts) walks a contiguous run of tiles of
+//   `tp` particles.
 //   Phase 1 evaluates each particle's basis once, one particle per lane.  The basis
 //   is split into independent jobs -- the Gegenbauer row of one l (radial job) and
 //   the Legendre column of one m times (cos, sin)(m phi) and the radial prefactor
-//   (angular job) -- and a compile-time plan gives each job to one wavefront, so the
-//   four wavefronts share the work of the same 64 particles.  The values go to LDS
-//   at compile-time offsets.
+//   (angular job) -- and a compile-time plan gives each job to one wavefront of a
+//   particle group: the four wavefronts share the work of the same 64 particles, or
+//   (small cutoffs, NW = 2 or 1) form 2 or 4 groups of 64 particles.  The values go to
+//   LDS at compile-time offsets.
 //   Phase 2 is an outer-product accumulation over the tile: every lane owns an
 //   nb x bs register block of coefficients (radial orders x angular slots of one l)
 //   and accumulates the products of the LDS-staged radial and angular values.  The

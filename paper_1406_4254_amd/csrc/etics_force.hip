@@ -7,8 +7,10 @@
 // lane, stream through the scalar cache into SGPR operands of the FMAs; the l and m
 // loops are compile-time, so the recurrence and derivative constants are instruction
 // literals.  The angular synthesis uses division-free identities for dYbar/dtheta
-// and m Ybar/sin(theta), and the result is rotated to Cartesian components.  No MFMA:
-// the work is basis evaluation and short reductions with ragged shapes.
+// and m Ybar/sin(theta), and the result is rotated to Cartesian components.  In the
+// batched leapfrog the epilogue applies the kicks (and drift) to the particle instead
+// of storing its acceleration.  No MFMA: the work is basis evaluation and short
+// reductions with ragged shapes.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -32,8 +32,7 @@ inline int coeff_count(int nmax, int lmax) { return (nmax + 1) * lm_count(lmax);
 // ---------------------------------------------------------------- SCF plan
 // Tile configuration of the coefficient kernel (chosen per (nmax, lmax, precision)).
 constexpr int kCoeffThreads = 256;  // 4 wavefronts
-constexpr int kMaxJobs = 32;        // basis jobs per wavefront (2 (lmax+1) <= 30)
-constexpr int kMaxStreams = 32;
+constexpr int kMaxStreams = 32;      // stream copies merged one after another at the end
 constexpr int kUnitParticles = 4096;  // batched work unit: particles of one system
 
 struct CoeffPlan {
