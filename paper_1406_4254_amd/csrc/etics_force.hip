@@ -126,7 +126,11 @@ __device__ __forceinline__ void force_point(const ForceArgs& a, const T* __restr
       // radial sums over n: U,V (potential), W,X (radial derivative).  Order 0 is taken
       // in closed form (Chat_0 = 1; it adds nothing to W, X since Ehat_{-1} = 0), the
       // loop starts at order 1.
-      const T* cfl = cf + l * (l + 1) / 2;
+      // the prepared coefficients are read-only here: through the constant address
+      // space their wave-uniform loads become scalar loads into SGPR operands (for FP64
+      // as well, where the generic pointer left the compiler with per-lane loads)
+      const __attribute__((address_space(4))) T* cfl =
+          (const __attribute__((address_space(4))) T*)(cf) + l * (l + 1) / 2;
       T U[l + 1], V[l + 1], W[l + 1], X[l + 1];
 #pragma unroll
       for (int m = 0; m <= l; ++m) {
@@ -143,7 +147,7 @@ __device__ __forceinline__ void force_point(const ForceArgs& a, const T* __restr
       auto step = [&](int nn, T& cA, T& cB, T& eA, T& eB) {
         // on entry cA = Chat_{nn-2}, cB = Chat_{nn-1}; on exit cA = Chat_nn
         cA = s.xi * cB - ql[nn] * cA;
-        const T* cn = cfl + nn * L2;
+        const auto* cn = cfl + nn * L2;
 #pragma unroll
         for (int m = 0; m <= l; ++m) {
           U[m] = fma_(cA, cn[m], U[m]);
