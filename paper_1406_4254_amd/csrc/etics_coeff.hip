@@ -194,6 +194,12 @@ __device__ __forceinline__ void decode_block(int b, int lmax, int nchunks, int& 
   }
 }
 
+// plain vector types for reads through LDS (address space 3) pointers
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) f32x4 LdsF32x4;
+typedef __attribute__((address_space(3))) f64x2 LdsF64x2;
+
 // One workgroup's share of the coefficient sums: the LDS tile, the register block
 // of each lane, and the three steps (basis -> LDS, accumulate, merge and write).
 template <typename T, int LB, int NB, int BS, int MODE, int NW>
@@ -208,6 +214,7 @@ struct CoeffWG {
   T* Z;  // [tp][SPZ]  angular values x mass x radial prefactor
   int tid, lane, wave, rank, pidx, maxm_w, lmax, nmax, tp, streams, nblocks, nchunks;
   int my_stream, my_block, bl, n0, s0;
+  int goff, zoff0;  // this lane's block in a particle's radial / angular row
   bool active;
   T acc[NB][BS];
   Wide<T, MODE> wide[NB][BS];
@@ -237,6 +244,8 @@ struct CoeffWG {
     my_block = tid - my_stream * nblocks;
     active = my_stream < streams;
     decode_block<NB, BS>(my_block, lmax, nchunks, bl, n0, s0);
+    goff = bl * NRP + n0;
+    zoff0 = zoff_rt<BS>(bl) + s0;
     clear_acc();
     clear_wide();
   }
@@ -306,7 +315,7 @@ struct CoeffWG {
         }
       }
       if (rank == kJP.ownerZ[m] && m <= lmax) {
-        T P2 = T(0), P1 = Pd;
+        T P2 = T(0), P1 = Pd;  // P2 is first read at l = m + 2
         auto put = [&](auto lc2, T P) {
           constexpr int l = decltype(lc2)::value;
           if constexpr (m == 0) {
@@ -315,15 +324,16 @@ struct CoeffWG {
             store_pair(Zp + zoff(l, BS) + 2 * m - 2, P * cmc, P * smc);
           }
         };
+        // the whole column up to the bucket's LB (rows past lmax are never read), so
+        // the recurrence runs without a branch per row
         put(std::integral_constant<int, m>{}, P1);
         static_for<LB - m>([&](auto kc) {
           constexpr int l = m + 1 + decltype(kc)::value;
-          if (l <= lmax) {
-            const T P = (T(kTab.c1[l][m]) * ctu) * P1 - (T(kTab.c2[l][m]) * tu2) * P2;
-            P2 = P1;
-            P1 = P;
-            put(std::integral_constant<int, l>{}, P);
-          }
+          T P = (T(kTab.c1[l][m]) * ctu) * P1;
+          if constexpr (l > m + 1) P -= (T(kTab.c2[l][m]) * tu2) * P2;
+          P2 = P1;
+          P1 = P;
+          put(std::integral_constant<int, l>{}, P);
         });
       }
     });
@@ -359,20 +369,22 @@ struct CoeffWG {
     });
   }
 
-  // phase 2: outer-product accumulation over the tile
+  // phase 2: outer-product accumulation over the tile.  LDS positions are 32-bit
+  // element offsets from the tile base.
   __device__ __forceinline__ void phase2() {
     if (!active) return;
-    const T* gbase = G + bl * NRP + n0;
-    const T* zbase = Z + zoff_rt<BS>(bl) + s0;
+    using LT = __attribute__((address_space(3))) const T;
+    LT* gs = (LT*)(G);
+    LT* zs = (LT*)(Z);
     constexpr int NG = (NB + 3) / 4 * 4;
     T gv[2][NG], zv[2][BS];
-    auto fetch = [&](int p, int buf) {
-      const T* g = gbase + p * SPG;
-      const T* zz = zbase + p * SPZ;
+    auto fetch = [&](int go, int zo, int buf) {
+      LT* g = gs + go;
+      LT* zz = zs + zo;
       if constexpr (sizeof(T) == 4) {
 #pragma unroll
         for (int q = 0; q < NG / 4; ++q) {
-          const float4 f = reinterpret_cast<const float4*>(g)[q];
+          const f32x4 f = reinterpret_cast<const LdsF32x4*>(g)[q];
           gv[buf][4 * q] = f.x;
           gv[buf][4 * q + 1] = f.y;
           gv[buf][4 * q + 2] = f.z;
@@ -381,7 +393,7 @@ struct CoeffWG {
       } else {
 #pragma unroll
         for (int q = 0; q < (NB + 1) / 2; ++q) {
-          const double2 f = reinterpret_cast<const double2*>(g)[q];
+          const f64x2 f = reinterpret_cast<const LdsF64x2*>(g)[q];
           gv[buf][2 * q] = f.x;
           gv[buf][2 * q + 1] = f.y;
         }
@@ -390,14 +402,14 @@ struct CoeffWG {
 #pragma unroll
       for (int j = 0; j < BS; j += 4) {
         if constexpr (sizeof(T) == 4) {
-          const float4 f = reinterpret_cast<const float4*>(zz)[j / 4];
+          const f32x4 f = reinterpret_cast<const LdsF32x4*>(zz)[j / 4];
           zv[buf][j] = f.x;
           zv[buf][j + 1] = f.y;
           zv[buf][j + 2] = f.z;
           zv[buf][j + 3] = f.w;
         } else {
-          const double2 f0 = reinterpret_cast<const double2*>(zz)[j / 2];
-          const double2 f1 = reinterpret_cast<const double2*>(zz)[j / 2 + 1];
+          const f64x2 f0 = reinterpret_cast<const LdsF64x2*>(zz)[j / 2];
+          const f64x2 f1 = reinterpret_cast<const LdsF64x2*>(zz)[j / 2 + 1];
           zv[buf][j] = f0.x;
           zv[buf][j + 1] = f0.y;
           zv[buf][j + 2] = f1.x;
@@ -414,14 +426,17 @@ struct CoeffWG {
     // two particles per trip, each one's LDS reads issued before the other's FMAs.  The
     // look-ahead read past the tile is clamped to its last particle (read, never used),
     // so the reads need no branch and the two buffers keep their registers.
-    const int last = tp - 1;
+    const int gstep = streams * SPG, zstep = streams * SPZ;
+    const int glast = goff + (tp - 1) * SPG, zlast = zoff0 + (tp - 1) * SPZ;
     int p = my_stream;
-    fetch(p < last ? p : last, 0);
+    int go = goff + p * SPG, zo = zoff0 + p * SPZ;
+    fetch(go < glast ? go : glast, zo < zlast ? zo : zlast, 0);
     for (; p + streams < tp; p += 2 * streams) {
-      fetch(p + streams, 1);
+      fetch(go + gstep, zo + zstep, 1);
       madd(0);
-      const int q = p + 2 * streams;
-      fetch(q < last ? q : last, 0);
+      go += 2 * gstep;
+      zo += 2 * zstep;
+      fetch(go < glast ? go : glast, zo < zlast ? zo : zlast, 0);
       madd(1);
     }
     if (p < tp) madd(0);
