@@ -39,6 +39,11 @@
 namespace etics {
 
 constexpr int kMexTile = 128;       // sorted particles per tile (one per thread, 2 wavefronts)
+// LDS column of a tile in the tile-sum kernel: the rows in 16 groups of 8 (one group per
+// lane of a 16-lane DPP row), with 2 doubles of padding after every second group, so
+// the four 16-byte reads of a group by 8 neighbouring lanes fall on distinct banks
+constexpr int kMexColStride = kMexTile + 2 * (kMexTile / 16);  // 144 doubles
+__device__ __forceinline__ int mex_row_pos(int t) { return t + 2 * (t >> 4); }
 constexpr int kMexBlockTiles = 64;  // tiles per block of the tile-offset scan
 constexpr int kSortSeg = 4096;      // keys per radix block
 constexpr int kSortThreads = 256;
@@ -266,6 +271,14 @@ __device__ __forceinline__ double wave_incl_prefix(double x) {
   x += dpp_move<kDppRowBcast31, 0xc>(x);  // lane 31 into rows 2, 3
   return x;
 }
+// inclusive prefix inside each row of 16 lanes
+__device__ __forceinline__ double row16_incl_prefix(double x) {
+  x += dpp_move<kDppRowShr1, 0xf>(x);
+  x += dpp_move<kDppRowShr2, 0xf>(x);
+  x += dpp_move<kDppRowShr4, 0xf>(x);
+  x += dpp_move<kDppRowShr8, 0xf>(x);
+  return x;
+}
 // exclusive prefix over lanes 0..lane-1 (0 in lane 0)
 __device__ __forceinline__ double wave_excl_prefix(double x) {
   return dpp_move<kDppWaveShr1, 0xf>(wave_incl_prefix(x));
@@ -277,6 +290,17 @@ __device__ __forceinline__ double wave_sum(double x) {
   const int hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
   return __longlong_as_double((static_cast<long long>(hi) << 32) |
                               static_cast<long long>(static_cast<unsigned int>(lo)));
+}
+
+// The 8 rows of group g of a padded column (rows 8g .. 8g+7), four 16-byte reads
+__device__ __forceinline__ void mex_group_read(const double* col, int g, double (&v)[8]) {
+  const double2* p = reinterpret_cast<const double2*>(col + mex_row_pos(8 * g));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 w = p[i];
+    v[2 * i] = w.x;
+    v[2 * i + 1] = w.y;
+  }
 }
 
 template <typename T, int LB, int r>
@@ -321,14 +345,18 @@ struct MexLane {
   }
 };
 
-// tile sums of inward / outward summands
+// tile sums of inward / outward summands.  Each 16-lane row of a wavefront sums one
+// column: a lane adds its group of 8 rows in order, then a row tree of the 16 lane
+// sums; the last lane of the row holds the total.  The two wavefronts take 8 columns
+// per round.
 template <typename T, int LB>
 __global__ __launch_bounds__(kMexTile) void mex_tile_sums_kernel(const MexArgs<LB> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* S = reinterpret_cast<double*>(lds_raw);  // [2l+1][kMexTile], one side at a time
+  double* S = reinterpret_cast<double*>(lds_raw);  // [2l+1][kMexColStride], one side at a time
   constexpr int NC = mex_nc(LB);
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: scalar addressing
+  const int drow = lane >> 4, k = lane & 15;                // DPP row (column), group
   MexLane<T, LB> q;
   q.load(a, int64_t(blockIdx.x) * kMexTile + t);
   double rl = 1.0, rm = q.p.rinv;  // r^l, r^-(l+1)
@@ -340,17 +368,19 @@ __global__ __launch_bounds__(kMexTile) void mex_tile_sums_kernel(const MexArgs<L
     constexpr int H = 2 * l + 1;
     static_for<2>([&](auto sidec) {
       constexpr int side = decltype(sidec)::value;
-      mex_summands_col<T, LB, l, side, kMexTile>(q.p, q.Y, q.cm, q.sm, rl, rm, q.valid, S + t);
+      mex_summands_col<T, LB, l, side, kMexColStride>(q.p, q.Y, q.cm, q.sm, rl, rm, q.valid,
+                                                      S + mex_row_pos(t));
       __syncthreads();
-      // one wavefront per column: two rows per lane, then a lane tree; the columns of a
-      // wavefront are independent and unrolled so their trees interleave
-      static_for<(H + 1) / 2>([&](auto jc) {
-        const int c = 2 * decltype(jc)::value + wave;
-        if (c < H) {
-          const double2 v = *reinterpret_cast<const double2*>(S + c * kMexTile + 2 * lane);
-          const double tot = wave_sum(v.x + v.y);
-          if (lane == 0) out[side * NC + mex_coff(l) + c] = tot;
-        }
+      static_for<(H + 7) / 8>([&](auto jc) {
+        const int c = 8 * decltype(jc)::value + 4 * wave + drow;
+        const int cc = c < H ? c : H - 1;  // rows past the last column read a valid one
+        double v[8];
+        mex_group_read(S + cc * kMexColStride, k, v);
+        double sum = v[0];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) sum += v[i];
+        const double tot = row16_incl_prefix(sum);
+        if (k == 15 && c < H) out[side * NC + mex_coff(l) + c] = tot;
       });
       __syncthreads();
     });
@@ -587,10 +617,12 @@ MexLayout mex_layout(int64_t n, int lmax) {
 
 template <typename T, int LB>
 int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
-  // largest LDS block: 2l+1 columns (one side) of kMexTile doubles at l = LB
+  // largest LDS blocks: 2l+1 columns (one side) at l = LB, of kMexColStride (tile sums)
+  // or kMexTile (force) doubles; at most 29 columns of 144 doubles (33.4 KiB): within
+  // the default LDS limit
+  const size_t lds_sums = size_t(kMexColStride) * (2 * LB + 1) * 8;
   const size_t lds = size_t(kMexTile) * (2 * LB + 1) * 8;
-  // at most 2l+1 <= 29 columns of 128 doubles (29.7 KiB): within the default LDS limit
-  hipLaunchKernelGGL((mex_tile_sums_kernel<T, LB>), dim3(ntiles), dim3(kMexTile), lds, st, a);
+  hipLaunchKernelGGL((mex_tile_sums_kernel<T, LB>), dim3(ntiles), dim3(kMexTile), lds_sums, st, a);
   int rc = hip_fail(hipGetLastError(), "mex_tile_sums_kernel launch");
   if (rc) return rc;
   hipLaunchKernelGGL((mex_block_sums_kernel<LB>), dim3(a.nblocks), dim3(256), 0, st, a);

@@ -78,6 +78,28 @@ def test_mex_ties_keep_index_order(E, orc):
     check("mex ties", got, ref, 1e-12, 1e-11, 1e-9)
 
 
+def test_mex_near_ties_below_key_precision(E, orc):
+    """A cluster whose radii differ by ~2^-40 relative (below FP32 resolution) placed
+    in reverse index order.  The force on a particle changes by a whole pair term
+    (order m_j / r^2) when a near neighbour moves from inward to outward, so the order
+    must follow the exact FP64 key, not a rounded one or the index."""
+    p = W.make_config(4, 2000)
+    rng = np.random.default_rng(41)
+    k = 16
+    r0 = 0.7
+    r = r0 * (1.0 + (k - 1 - np.arange(k)) * 2.0 ** -40)   # decreasing with index
+    ct = rng.uniform(-1.0, 1.0, k)
+    st = np.sqrt(1.0 - ct * ct)
+    ph = rng.uniform(0.0, 2.0 * np.pi, k)
+    x = np.concatenate([p.x, r * st * np.cos(ph)])
+    y = np.concatenate([p.y, r * st * np.sin(ph)])
+    z = np.concatenate([p.z, r * ct])
+    m = np.full(x.size, 1.0 / x.size)
+    got = gpu_mex(E, x, y, z, m, 6, FP64)
+    ref = orc.mex_force(x, y, z, m, 6)
+    check("mex near ties", got, ref, 1e-12, 1e-11, 1e-9)
+
+
 def test_mex_origin_particle(E, orc):
     p = W.make_config(4, 700)
     x, y, z = p.x.copy(), p.y.copy(), p.z.copy()
