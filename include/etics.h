@@ -117,6 +117,18 @@ int etics_mex_force(const double* x, const double* y, const double* z, const dou
                     double* pot, double* ax, double* ay, double* az,
                     void* workspace, size_t ws_bytes, void* stream);
 
+/* Direct summation without softening, in FP64: the N-body force that the accuracy
+   study of Section 4.1 compares with the expansions and with the smooth force of the
+   model.  pot[i] = -sum m_j / r_ij and a_i = sum m_j (x_j - x_i) / r_ij^3 over all j
+   with r_ij > 0 (G = 1): the particle itself, and any particle at exactly the same
+   position, adds nothing.  Inputs as for the calls above (DEVICE arrays of n);
+   outputs as selected by `outputs` (arrays the caller owns; unselected ones may be
+   NULL).  No workspace; O(n^2) work.  Errors: ETICS_EINVAL for n < 0 or n > 2^40, a
+   bad `outputs` or a NULL array that is needed; ETICS_EHIP for a launch failure. */
+int etics_direct_force(const double* x, const double* y, const double* z, const double* m,
+                       int64_t n, int outputs, double* pot, double* ax, double* ay, double* az,
+                       void* stream);
+
 /* Workspace bytes for the batched SCF calls and the batched leapfrog over nsys
    systems with ntotal particles in all; 0 if the arguments are invalid. */
 size_t etics_batched_workspace_size(int64_t ntotal, int nsys, int nmax, int lmax, int precision);

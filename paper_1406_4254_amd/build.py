@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libetics.so")
 
-SOURCES = ["etics_coeff.hip", "etics_force.hip", "etics_mex.hip", "etics_batched.hip", "etics_abi.cpp"]
+SOURCES = ["etics_coeff.hip", "etics_force.hip", "etics_mex.hip", "etics_batched.hip", "etics_direct.hip",
+           "etics_abi.cpp"]
 ARCH = os.environ.get("ETICS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

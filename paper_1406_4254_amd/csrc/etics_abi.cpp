@@ -174,6 +174,21 @@ int etics_mex_force(const double* x, const double* y, const double* z, const dou
                           reinterpret_cast<hipStream_t>(stream));
 }
 
+// ---------------------------------------------------------------- direct summation
+int etics_direct_force(const double* x, const double* y, const double* z, const double* m,
+                       int64_t n, int outputs, double* pot, double* ax, double* ay, double* az,
+                       void* stream) {
+  if (n < 0) return einval("n < 0");
+  if (n > (int64_t(1) << 40)) return einval("n too large");
+  if (outputs < 1 || outputs > 3) return einval("outputs");
+  if (n > 0 && (!x || !y || !z || !m)) return einval("x/y/z/m is NULL");
+  if (n > 0 && (outputs & ETICS_POT) && !pot) return einval("pot is NULL");
+  if (n > 0 && (outputs & ETICS_ACC) && (!ax || !ay || !az)) return einval("ax/ay/az is NULL");
+  if (n == 0) return ETICS_OK;
+  return launch_direct_force(x, y, z, m, n, outputs, pot, ax, ay, az,
+                             reinterpret_cast<hipStream_t>(stream));
+}
+
 // ---------------------------------------------------------------- batched + leapfrog
 static int check_batched(int64_t ntotal, int nsys, int nmax, int lmax, int prec, const void* offsets) {
   if (ntotal < 0) return einval("ntotal < 0");

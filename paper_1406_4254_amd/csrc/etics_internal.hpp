@@ -99,5 +99,8 @@ size_t mex_ws_bytes(int64_t n, int lmax);
 int launch_mex_force(const double* x, const double* y, const double* z, const double* m, int64_t n,
                      int lmax, int prec, int outputs, double* pot, double* ax, double* ay,
                      double* az, void* ws, hipStream_t st);
+int launch_direct_force(const double* x, const double* y, const double* z, const double* m,
+                        int64_t n, int outputs, double* pot, double* ax, double* ay, double* az,
+                        hipStream_t st);
 
 }  // namespace etics

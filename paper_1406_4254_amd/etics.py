@@ -35,7 +35,7 @@ EXPORTED = [
     "etics_coeff_count", "etics_scf_workspace_size", "etics_scf_coeffs", "etics_scf_force",
     "etics_mex_workspace_size", "etics_mex_force", "etics_batched_workspace_size",
     "etics_scf_coeffs_batched", "etics_scf_force_batched", "etics_leapfrog_scf_batched",
-    "etics_set_timing_events", "etics_last_error", "etics_version",
+    "etics_direct_force", "etics_set_timing_events", "etics_last_error", "etics_version",
 ]
 
 
@@ -85,6 +85,8 @@ def lib():
                                                  _int, _int, _int, ctypes.c_double, _int, _int, _vp, _sz,
                                                  _vp]
         L.etics_leapfrog_scf_batched.restype = _int
+        L.etics_direct_force.argtypes = [_vp, _vp, _vp, _vp, _i64, _int, _vp, _vp, _vp, _vp, _vp]
+        L.etics_direct_force.restype = _int
         L.etics_set_timing_events.argtypes = [_vp, _vp]
         L.etics_set_timing_events.restype = _int
         L.etics_last_error.restype = ctypes.c_char_p
@@ -218,6 +220,24 @@ def etics_mex_force(x, y, z, m, lmax: int, precision=ETICS_MIXED_FP64ACC, output
     _check(lib().etics_mex_force(_ptr(x), _ptr(y), _ptr(z), _ptr(m), n, lmax, p, outputs,
                                  _ptr(pot), _ptr(ax), _ptr(ay), _ptr(az), _ptr(ws), ws.numel(),
                                  _stream(stream)))
+    return pot, ax, ay, az
+
+
+def etics_direct_force(x, y, z, m, outputs=ETICS_POT_ACC, pot=None, ax=None, ay=None, az=None,
+                       stream=None):
+    """Unsoftened FP64 direct-summation potential and acceleration (O(n^2))."""
+    for t, nm in ((x, "x"), (y, "y"), (z, "z"), (m, "m")):
+        _dev(t, nm)
+    n = x.numel()
+    mk = lambda: torch.empty(n, dtype=torch.float64, device=x.device)
+    if outputs & ETICS_POT:
+        pot = mk() if pot is None else _dev(pot, "pot")
+    if outputs & ETICS_ACC:
+        ax = mk() if ax is None else _dev(ax, "ax")
+        ay = mk() if ay is None else _dev(ay, "ay")
+        az = mk() if az is None else _dev(az, "az")
+    _check(lib().etics_direct_force(_ptr(x), _ptr(y), _ptr(z), _ptr(m), n, outputs, _ptr(pot), _ptr(ax),
+                                    _ptr(ay), _ptr(az), _stream(stream)))
     return pot, ax, ay, az
 
 

@@ -174,6 +174,36 @@ CONFIGS = {
 }
 
 
+# Ferrers ellipsoids of index 1 (the accuracy study of Section 4.1): density
+# rho0 (1 - mu^2/a^2) inside the ellipsoid mu <= a, mu^2 = x^2 + (a/b)^2 y^2 + (a/c)^2 z^2.
+# model1 is the 10:10:9 oblate spheroid, model2 the 3:2:1 triaxial ellipsoid; a = 1,
+# total mass 1.
+FERRERS_MODELS = {"model1": (1.0, 1.0, 0.9), "model2": (1.0, 2.0 / 3.0, 1.0 / 3.0)}
+
+
+def ferrers1(n, seed, axes=(1.0, 1.0, 0.9)):
+    """n particles of mass 1/n drawn from a Ferrers n=1 ellipsoid with the given axes.
+
+    The unit-ball variable s = mu/a has density proportional to s^2 (1 - s^2): s is
+    drawn as u^(1/3) (uniform ball) and kept with probability 1 - s^2 (rejection, in
+    rounds of draws until n are kept); directions are isotropic; the point is then
+    stretched by the axes."""
+    rng = np.random.default_rng(seed)
+    kept = []
+    have = 0
+    while have < n:
+        k = max(2 * (n - have) + 64, 1024)
+        s = rng.random(k) ** (1.0 / 3.0)
+        keep = rng.random(k) < 1.0 - s * s
+        kept.append(s[keep])
+        have += int(keep.sum())
+    s = np.concatenate(kept)[:n]
+    dx, dy, dz = _sphere_dirs(rng, n)
+    a, b, c = axes
+    x, y, z = a * s * dx, b * s * dy, c * s * dz
+    return Particles(x, y, z, np.full(n, 1.0 / n), meta=dict(model="ferrers1", axes=tuple(axes)))
+
+
 def make_config(cfg: int, n: int | None = None) -> Particles:
     """Particles of a named configuration; n overrides the size (same recipe and seed)."""
     c = CONFIGS[cfg]

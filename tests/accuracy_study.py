@@ -1,0 +1,78 @@
+"""The accuracy study of Section 4.1 on the GPU library: mean and median relative
+force error (eq. epsilon) of MEX, SCF and direct summation against the smooth force of
+the Ferrers n=1 models (model1 10:10:9, model2 3:2:1), all in FP64.
+
+Not collected by pytest (the test file test_gpu_direct.py checks the qualitative
+claims at two sizes); run it directly on a GPU machine:
+    python tests/accuracy_study.py [--sizes 1000 10000 100000 1000000]
+It prints one markdown table per model.  N = 1000 is stacked over 100 realizations
+(seeds 1000..1099); larger N use one realization (seed 41).
+"""
+import argparse
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import torch  # noqa: E402
+
+from oracle import ferrers as F  # noqa: E402
+from paper_1406_4254_amd import accuracy as acc  # noqa: E402
+from paper_1406_4254_amd import etics as E  # noqa: E402
+from paper_1406_4254_amd import workloads as W  # noqa: E402
+
+FP64 = 0
+MEX_L = (0, 2, 4, 6, 8, 10)
+SCF_N = (2, 6, 10, 20)
+
+
+def dev(*arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in arrs]
+
+
+def errors(p, axes):
+    real = F.force(p.x, p.y, p.z, axes)
+    d = dev(p.x, p.y, p.z, p.m)
+    out = {}
+    for lmax in MEX_L:
+        r = E.etics_mex_force(*d, lmax, FP64, 2)
+        out[f"MEX l{lmax}"] = acc.force_rel_err(*[t.cpu().numpy() for t in r[1:]], *real)
+    for nmax in SCF_N:
+        A, B = E.etics_scf_coeffs(*d, nmax, 10, FP64)
+        r = E.etics_scf_force(*d[:3], nmax, 10, A, B, FP64, 2)
+        out[f"SCF n{nmax} l10"] = acc.force_rel_err(*[t.cpu().numpy() for t in r[1:]], *real)
+    if p.n <= 1_000_000:
+        r = E.etics_direct_force(*d, outputs=2)
+        out["direct"] = acc.force_rel_err(*[t.cpu().numpy() for t in r[1:]], *real)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", type=int, nargs="+", default=[1000, 10_000, 100_000, 1_000_000])
+    args = ap.parse_args()
+    for model, axes in W.FERRERS_MODELS.items():
+        rows = {}
+        for n in args.sizes:
+            if n <= 1000:
+                parts = [errors(W.ferrers1(n, 1000 + k, axes), axes) for k in range(100)]
+                res = {key: np.concatenate([q[key] for q in parts]) for key in parts[0]}
+            else:
+                res = errors(W.ferrers1(n, 41, axes), axes)
+            for key, e in res.items():
+                rows.setdefault(key, {})[n] = (float(np.mean(e)), float(np.median(e)))
+            print(f"{model} N={n} done", flush=True)
+        print(f"\n{model} {axes}: mean / median relative force error vs the smooth force\n")
+        print("| method | " + " | ".join(f"N={n:g}" for n in args.sizes) + " |")
+        print("|---|" + "---|" * len(args.sizes))
+        for key, d in rows.items():
+            cells = [f"{d[n][0]:.2e} / {d[n][1]:.2e}" if n in d else "—" for n in args.sizes]
+            print(f"| {key} | " + " | ".join(cells) + " |")
+        print(flush=True)
+
+
+if __name__ == "__main__":
+    main()
