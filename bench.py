@@ -310,7 +310,8 @@ def main():
 
 
 def extras(torch, np, etics, workloads, stream, reps=10):
-    """MEX force (N = 10^6, lmax = 10) and the batched hipGraph leapfrog step."""
+    """MEX force (N = 10^6, lmax = 10), the batched hipGraph leapfrog step and the FP64
+    direct summation of the accuracy study (N = 10^5)."""
     ex = {}
     p = workloads.make_config(4)
     n = p.x.shape[0]
@@ -363,6 +364,30 @@ def extras(torch, np, etics, workloads, stream, reps=10):
                                     "ms_per_call": ms, "ms_per_step": step_ms,
                                     "particle_steps_per_s": nt * (nsteps + 1) / (ms * 1e-3),
                                     "step_tflops": (fc + ff) * nt / (step_ms * 1e-3) / 1e12}
+    del st, off, ws
+    # FP64 direct summation (the N-body reference of the accuracy study), N = 10^5
+    # Ferrers model2: 19 flops per pair (3 differences, 5 for r^2, 1 reciprocal square
+    # root, 3 for m/r and m/r^3, 1 for the potential, 6 for the acceleration)
+    pd = workloads.ferrers1(100_000, 41, workloads.FERRERS_MODELS["model2"])
+    nd = pd.n
+    x, y, z, m = (torch.from_numpy(a).cuda() for a in (pd.x, pd.y, pd.z, pd.m))
+    outs = [torch.empty(nd, dtype=torch.float64, device="cuda") for _ in range(4)]
+    call = lambda: etics.etics_direct_force(x, y, z, m, etics.ETICS_POT_ACC, *outs, stream=stream)
+    call()
+    dreps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(dreps):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / dreps
+    pairs = float(nd) * nd
+    tf = 19.0 * pairs / (ms * 1e-3) / 1e12
+    ex["direct_fp64"] = {"workload": "direct_ferrers_model2_n1e5", "ms_per_call": ms,
+                         "pairs_per_s": pairs / (ms * 1e-3), "flops_per_pair": 19,
+                         "achieved_tflops": tf, "frac_of_fp64_peak": tf / PEAK_FP64_VECTOR_TFLOPS}
     return ex
 
 

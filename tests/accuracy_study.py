@@ -50,18 +50,27 @@ def errors(p, axes):
     return out
 
 
+def overlap(e1, e2, bins=120, lo=-8.0, hi=2.0):
+    """Overlap of two error distributions: the integral of min(p1, p2) over log10 eps."""
+    h1, _ = np.histogram(np.log10(e1), bins=bins, range=(lo, hi))
+    h2, _ = np.histogram(np.log10(e2), bins=bins, range=(lo, hi))
+    return float(np.minimum(h1 / e1.size, h2 / e2.size).sum())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sizes", type=int, nargs="+", default=[1000, 10_000, 100_000, 1_000_000])
     args = ap.parse_args()
     for model, axes in W.FERRERS_MODELS.items():
         rows = {}
+        last = None
         for n in args.sizes:
             if n <= 1000:
                 parts = [errors(W.ferrers1(n, 1000 + k, axes), axes) for k in range(100)]
                 res = {key: np.concatenate([q[key] for q in parts]) for key in parts[0]}
             else:
                 res = errors(W.ferrers1(n, 41, axes), axes)
+            last = (n, res)
             for key, e in res.items():
                 rows.setdefault(key, {})[n] = (float(np.mean(e)), float(np.median(e)))
             print(f"{model} N={n} done", flush=True)
@@ -71,6 +80,10 @@ def main():
         for key, d in rows.items():
             cells = [f"{d[n][0]:.2e} / {d[n][1]:.2e}" if n in d else "—" for n in args.sizes]
             print(f"| {key} | " + " | ".join(cells) + " |")
+        if last is not None:
+            n, res = last
+            ov = ", ".join(f"n{k}: {overlap(res[f'SCF n{k} l10'], res['MEX l10']):.0%}" for k in SCF_N)
+            print(f"\noverlap of the SCF (l10) and MEX l10 error distributions at N={n:g}: {ov}")
         print(flush=True)
 
 
