@@ -365,6 +365,38 @@ def extras(torch, np, etics, workloads, stream, reps=10):
                                     "particle_steps_per_s": nt * (nsteps + 1) / (ms * 1e-3),
                                     "step_tflops": (fc + ff) * nt / (step_ms * 1e-3) / 1e12}
     del st, off, ws
+    # potential only (no acceleration): the SCF step of the headline workload with the
+    # force call asked for ETICS_POT, which runs the kernel without the derivative sums
+    p2 = workloads.make_config(2)
+    n2 = p2.n
+    x, y, z, m = (torch.from_numpy(a).cuda() for a in (p2.x, p2.y, p2.z, p2.m))
+    prec = etics.ETICS_MIXED_FP64ACC
+    K = etics.etics_coeff_count(10, 10)
+    A = torch.empty(K, dtype=torch.float64, device="cuda")
+    B = torch.empty_like(A)
+    pot = torch.empty(n2, dtype=torch.float64, device="cuda")
+    ws = etics.workspace(etics.etics_scf_workspace_size(n2, 10, 10, prec), "cuda")
+
+    def pstep():
+        etics.etics_scf_coeffs(x, y, z, m, 10, 10, prec, A, B, ws, stream)
+        etics.etics_scf_force(x, y, z, 10, 10, A, B, prec, etics.ETICS_POT, pot, None, None, None, ws, stream)
+
+    pstep()
+    kt = KernelTimer(torch, etics, reps, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        etics.etics_scf_coeffs(x, y, z, m, 10, 10, prec, A, B, ws, stream)
+        kt.arm()
+        etics.etics_scf_force(x, y, z, 10, 10, A, B, prec, etics.ETICS_POT, pot, None, None, None, ws, stream)
+        etics.etics_set_timing_events(None, None)  # the next coefficient call is not timed
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ex["scf_potential_only_mixed"] = {"workload": "scf_triaxial_hernquist_n1e6_n10_l10", "ms_per_step": ms,
+                                      "particles_per_s": n2 / (ms * 1e-3), "force_kernel_ms": kt.mean_ms()}
+    del x, y, z, m, A, B, pot, ws
     # FP64 direct summation (the N-body reference of the accuracy study), N = 10^5
     # Ferrers model2: 19 flops per pair (3 differences, 5 for r^2, 1 reciprocal square
     # root, 3 for m/r and m/r^3, 1 for the potential, 6 for the acceleration)
