@@ -123,7 +123,7 @@ int etics_mex_force(const double* x, const double* y, const double* z, const dou
    with r_ij > 0 (G = 1): the particle itself, and any particle at exactly the same
    position, adds nothing.  Inputs as for the calls above (DEVICE arrays of n);
    outputs as selected by `outputs` (arrays the caller owns; unselected ones may be
-   NULL).  No workspace; O(n^2) work.  Errors: ETICS_EINVAL for n < 0 or n > 2^40, a
+   NULL).  No workspace; O(n^2) work.  Errors: ETICS_EINVAL for n < 0 or n >= 2^31, a
    bad `outputs` or a NULL array that is needed; ETICS_EHIP for a launch failure. */
 int etics_direct_force(const double* x, const double* y, const double* z, const double* m,
                        int64_t n, int outputs, double* pot, double* ax, double* ay, double* az,

@@ -179,7 +179,7 @@ int etics_direct_force(const double* x, const double* y, const double* z, const 
                        int64_t n, int outputs, double* pot, double* ax, double* ay, double* az,
                        void* stream) {
   if (n < 0) return einval("n < 0");
-  if (n > (int64_t(1) << 40)) return einval("n too large");
+  if (n > INT32_MAX) return einval("n must be below 2^31");
   if (outputs < 1 || outputs > 3) return einval("outputs");
   if (n > 0 && (!x || !y || !z || !m)) return einval("x/y/z/m is NULL");
   if (n > 0 && (outputs & ETICS_POT) && !pot) return einval("pot is NULL");

@@ -95,6 +95,22 @@ def test_invalid_arguments_rejected_without_device_work(L):
              ctypes.c_void_p(0x1008), 1 << 30, None) == -1
 
 
+def test_direct_force_arguments_rejected_without_device_work(L):
+    d = L.etics_direct_force
+    d.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_int] + [ctypes.c_void_p] * 5
+    L.etics_last_error.restype = ctypes.c_char_p
+    fake = ctypes.c_void_p(0x1000)
+    assert d(fake, fake, fake, fake, -1, 3, fake, fake, fake, fake, None) == -1
+    assert d(fake, fake, fake, fake, 1 << 31, 3, fake, fake, fake, fake, None) == -1
+    assert d(fake, fake, fake, fake, 10, 0, fake, fake, fake, fake, None) == -1
+    assert d(fake, fake, fake, None, 10, 3, fake, fake, fake, fake, None) == -1
+    assert d(fake, fake, fake, fake, 10, 1, None, None, None, None, None) == -1
+    assert d(fake, fake, fake, fake, 10, 2, None, fake, None, fake, None) == -1
+    assert b"NULL" in L.etics_last_error()
+    # n = 0 is valid and does nothing (no device work, NULL arrays allowed)
+    assert d(None, None, None, None, 0, 3, None, None, None, None, None) == 0
+
+
 def test_version(L):
     L.etics_version.restype = ctypes.c_char_p
     assert b"gfx950" in L.etics_version()
