@@ -18,12 +18,13 @@
 //      scatter whose in-block ranks come from wavefront ballots.  Stable, so equal keys
 //      stay in index order.
 //   3. mex_tile_sums: per tile of sorted particles, the sums of the inward and outward
-//      summands (FP64).
+//      summands (FP64); each 16-lane row of a wavefront sums one LDS column, a lane
+//      adding 8 consecutive rows before a row tree.
 //   4. tile offsets: exclusive prefix (inward) and suffix (outward) over tiles, in
 //      three parallel steps (sums of blocks of tiles, a scan over the blocks, then the
 //      tiles of every block).
 //   5. mex_force: per tile, the summands again, exclusive scans inside the tile (each
-//      column staged in LDS, scanned by one wavefront with shuffles), plus the tile
+//      column staged in LDS, scanned by one wavefront with DPP lane moves), plus the tile
 //      offsets, give q and p of every particle; then the synthesis and the Cartesian
 //      force, scattered back to the caller's order.
 // Radial powers, moments, scans and synthesis accumulations are FP64 in every mode;
