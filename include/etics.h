@@ -67,9 +67,9 @@ extern "C" {
 #define ETICS_EINVAL (-1)        /* bad size, cutoff, mode or a required NULL pointer */
 #define ETICS_EWORKSPACE (-2)    /* workspace missing or smaller than required */
 #define ETICS_EHIP (-3)          /* a HIP runtime or launch error */
-#define ETICS_EUNSUPPORTED (-4)  /* valid request this build does not implement */
+#define ETICS_EUNSUPPORTED (-4)  /* valid request the library does not implement */
 
-/* expansion cutoffs supported by this build */
+/* expansion cutoffs supported by the library */
 #define ETICS_NMAX_CAP 20
 #define ETICS_LMAX_CAP 14
 
