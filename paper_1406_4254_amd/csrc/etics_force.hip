@@ -267,22 +267,30 @@ __global__ __launch_bounds__(256) void scf_force_kernel(const ForceArgs a) {
     force_point<T, LB, ACC>(a, cf, i);
 }
 
-// batched systems: one workgroup per unit of one system, so the coefficient pointer
-// (and with it every coefficient operand) is uniform across the workgroup
+// batched systems: kForceSplit workgroups per unit of one system (each a contiguous
+// part of it), so the coefficient pointer (and with it every coefficient operand) is
+// uniform across the workgroup; splitting the coefficient kernel's units gives the
+// force pass more workgroups
+constexpr int kForceSplit = 4;
+
 template <typename T, int LB, bool ACC>
 __global__ __launch_bounds__(256) void scf_force_batched_kernel(const ForceArgs a,
                                                                 const int64_t* __restrict__ offsets,
                                                                 const int* __restrict__ ustart,
                                                                 const int* __restrict__ usys,
                                                                 int nsys) {
-  const int u = blockIdx.x;
+  const int u = blockIdx.x / kForceSplit;
+  const int part = blockIdx.x % kForceSplit;
   if (u >= ustart[nsys]) return;
   const int sys = usys[u];
   int64_t b = offsets[sys], e = offsets[sys + 1];
   b = b < 0 ? 0 : (b > a.n ? a.n : b);
   e = e < b ? b : (e > a.n ? a.n : e);
-  const int64_t ub = b + int64_t(u - ustart[sys]) * kUnitParticles;
-  const int64_t ue = ub + kUnitParticles < e ? ub + kUnitParticles : e;
+  constexpr int64_t kPart = kUnitParticles / kForceSplit;
+  const int64_t u0 = b + int64_t(u - ustart[sys]) * kUnitParticles;
+  const int64_t ue0 = u0 + kUnitParticles < e ? u0 + kUnitParticles : e;
+  const int64_t ub = u0 + part * kPart < ue0 ? u0 + part * kPart : ue0;
+  const int64_t ue = ub + kPart < ue0 ? ub + kPart : ue0;
   const T* __restrict__ cf = reinterpret_cast<const T*>(a.cf) + size_t(sys) * 4 * a.K;
   for (int64_t i = ub + threadIdx.x; i < ue; i += blockDim.x) force_point<T, LB, ACC>(a, cf, i);
 }
@@ -397,7 +405,7 @@ int launch_scf_force_batched(const double* x, const double* y, const double* z,
   ForceArgs a = make_force_args(x, y, z, ntotal, nmax, lmax, outputs, pot, ax, ay, az, prep);
   if (lf) a.lf = *lf;
   const BatchInfo bi{offsets, ustart, usys, nsys};
-  return launch_force_any(a, prec, outputs, max_units(ntotal, nsys), &bi, st);
+  return launch_force_any(a, prec, outputs, max_units(ntotal, nsys) * kForceSplit, &bi, st);
 }
 
 }  // namespace etics
