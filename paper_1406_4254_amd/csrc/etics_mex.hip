@@ -45,7 +45,7 @@ constexpr int kMexTile = 128;       // sorted particles per tile (one per thread
 // the four 16-byte reads of a group by 8 neighbouring lanes fall on distinct banks
 constexpr int kMexColStride = kMexTile + 2 * (kMexTile / 16);  // 144 doubles
 __device__ __forceinline__ int mex_row_pos(int t) { return t + 2 * (t >> 4); }
-constexpr int kMexBlockTiles = 64;  // tiles per block of the tile-offset scan
+constexpr int kMexBlockTiles = 16;  // tiles per block of the tile-offset scan
 constexpr int kSortSeg = 4096;      // keys per radix block
 constexpr int kSortThreads = 256;
 
