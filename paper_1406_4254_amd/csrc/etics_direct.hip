@@ -39,7 +39,11 @@ __global__ __launch_bounds__(kDirectThreads) void direct_force_kernel(
       const double4 s = src[k];
       const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
       const double r2 = dx * dx + dy * dy + dz * dz;
-      const double rinv = r2 > 0.0 ? rsqrt(r2) : 0.0;
+      // the reciprocal square root runs for every pair (of 1 at zero separation), and
+      // a select drops the pairs at zero separation: no branch in the loop
+      const bool apart = r2 > 0.0;
+      const double rs = rsqrt(apart ? r2 : 1.0);
+      const double rinv = apart ? rs : 0.0;
       const double mr = s.w * rinv;
       const double mr3 = mr * rinv * rinv;
       P -= mr;
