@@ -20,30 +20,45 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "etics_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source with long-double running sums: measures the rounding of the plain
+# oracle's own sequential sums (each term is still formed in double)
+_LIB_EXT = os.path.join(_HERE, "liboracle_ld.so")
 _lib = None
+_lib_ext = None
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)
 
 
-def build() -> str:
-    """Compile etics_oracle.c into liboracle.so (gcc, -O2, OpenMP, no fast-math)."""
+def _build_one(out: str, extra) -> None:
     cmd = [
         "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-        "-ffp-contract=off", "-fno-fast-math", "-Wall",
-        _SRC, "-o", _LIB + ".tmp", "-lm",
+        "-ffp-contract=off", "-fno-fast-math", "-Wall", *extra,
+        _SRC, "-o", out + ".tmp", "-lm",
     ]
     subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
+    os.replace(out + ".tmp", out)
+
+
+def build() -> str:
+    """Compile etics_oracle.c into liboracle.so (gcc, -O2, OpenMP, no fast-math) and
+    into liboracle_ld.so (the same with long-double running sums)."""
+    _build_one(_LIB, [])
+    _build_one(_LIB_EXT, ["-DORACLE_ACC=long double"])
     return _LIB
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+def _stale(path: str) -> bool:
+    return not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC)
+
+
+def lib(ext: bool = False):
+    """The oracle library; ext=True: the build with long-double running sums."""
+    global _lib, _lib_ext
+    if (_lib_ext if ext else _lib) is None:
+        if _stale(_LIB) or _stale(_LIB_EXT):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_LIB_EXT if ext else _LIB)
         L.oracle_gegenbauer.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]
         L.oracle_ylm.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]
         L.oracle_ylm_deriv.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _D, _D, _D]
@@ -69,8 +84,11 @@ def lib():
                                           ctypes.c_int, ctypes.c_double, ctypes.c_int]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
-        _lib = L
-    return _lib
+        if ext:
+            _lib_ext = L
+        else:
+            _lib = L
+    return _lib_ext if ext else _lib
 
 
 def _dp(a):
@@ -135,19 +153,20 @@ def rho_nl(nmax: int, lmax: int, r: float) -> np.ndarray:
     return rho.reshape(nmax + 1, lmax + 1)
 
 
-def scf_coeffs(x, y, z, m, nmax: int, lmax: int):
+def scf_coeffs(x, y, z, m, nmax: int, lmax: int, ext: bool = False):
+    """ext=True: the same sums with long-double accumulators."""
     x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
     K = coeff_count(nmax, lmax)
     A, B = np.zeros(K), np.zeros(K)
-    lib().oracle_scf_coeffs(_dp(x), _dp(y), _dp(z), _dp(m), len(x), nmax, lmax, _dp(A), _dp(B))
+    lib(ext).oracle_scf_coeffs(_dp(x), _dp(y), _dp(z), _dp(m), len(x), nmax, lmax, _dp(A), _dp(B))
     return A, B
 
 
-def scf_force(x, y, z, nmax: int, lmax: int, A, B):
+def scf_force(x, y, z, nmax: int, lmax: int, A, B, ext: bool = False):
     x, y, z, A, B = _f64(x), _f64(y), _f64(z), _f64(A), _f64(B)
     n = len(x)
     pot, ax, ay, az = (np.zeros(n) for _ in range(4))
-    lib().oracle_scf_force(_dp(x), _dp(y), _dp(z), n, nmax, lmax, _dp(A), _dp(B),
+    lib(ext).oracle_scf_force(_dp(x), _dp(y), _dp(z), n, nmax, lmax, _dp(A), _dp(B),
                            _dp(pot), _dp(ax), _dp(ay), _dp(az))
     return pot, ax, ay, az
 
@@ -163,11 +182,11 @@ def mex_order(x, y, z) -> np.ndarray:
     return order
 
 
-def mex_force(x, y, z, m, lmax: int):
+def mex_force(x, y, z, m, lmax: int, ext: bool = False):
     x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
     n = len(x)
     pot, ax, ay, az = (np.zeros(n) for _ in range(4))
-    lib().oracle_mex_force(_dp(x), _dp(y), _dp(z), _dp(m), n, lmax,
+    lib(ext).oracle_mex_force(_dp(x), _dp(y), _dp(z), _dp(m), n, lmax,
                            _dp(pot), _dp(ax), _dp(ay), _dp(az))
     return pot, ax, ay, az
 

@@ -45,6 +45,14 @@
 #define M_PI 3.14159265358979323846
 #endif
 #define FOUR_PI (4.0 * M_PI)
+/* Type of every running sum over particles or over expansion terms.  The oracle is
+   built with plain double; a second build with long double measures how much of the
+   oracle's own result is rounding of its sequential sums (each term is still formed
+   in double, so only the additions differ). */
+#ifndef ORACLE_ACC
+#define ORACLE_ACC double
+#endif
+typedef ORACLE_ACC acc_t;
 /* fixed particle chunking for the coefficient sums: the result does not depend on
    the number of threads that happen to run the chunks */
 #define ORACLE_NCHUNK 64
@@ -225,8 +233,8 @@ void oracle_scf_coeffs(const double *x, const double *y, const double *z, const 
                        int64_t np, int nmax, int lmax, double *A, double *B) {
   int K = oracle_coeff_count(nmax, lmax);
   int L2 = (lmax + 1) * (lmax + 2) / 2;
-  double *SA = (double *)calloc((size_t)ORACLE_NCHUNK * K, sizeof(double));
-  double *SB = (double *)calloc((size_t)ORACLE_NCHUNK * K, sizeof(double));
+  acc_t *SA = (acc_t *)calloc((size_t)ORACLE_NCHUNK * K, sizeof(acc_t));
+  acc_t *SB = (acc_t *)calloc((size_t)ORACLE_NCHUNK * K, sizeof(acc_t));
 #pragma omp parallel for schedule(dynamic, 1)
   for (int ch = 0; ch < ORACLE_NCHUNK; ++ch) {
     int64_t j0 = np * ch / ORACLE_NCHUNK, j1 = np * (ch + 1) / ORACLE_NCHUNK;
@@ -234,7 +242,7 @@ void oracle_scf_coeffs(const double *x, const double *y, const double *z, const 
     double *Y = (double *)malloc(sizeof(double) * (size_t)L2);
     double *cm = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
     double *sm = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
-    double *sa = SA + (size_t)ch * K, *sb = SB + (size_t)ch * K;
+    acc_t *sa = SA + (size_t)ch * K, *sb = SB + (size_t)ch * K;
     for (int64_t j = j0; j < j1; ++j) {
       /* (1a) special functions of this particle */
       sph_t s = to_sph(x[j], y[j], z[j]);
@@ -251,8 +259,8 @@ void oracle_scf_coeffs(const double *x, const double *y, const double *z, const 
           double w = mass[j] * phi[n * (lmax + 1) + l];
           for (int m = 0; m <= l; ++m) {
             int k = n * L2 + lm_index(l, m);
-            sa[k] += w * Y[lm_index(l, m)] * cm[m];
-            sb[k] += w * Y[lm_index(l, m)] * sm[m];
+            sa[k] += (acc_t)(w * Y[lm_index(l, m)] * cm[m]);
+            sb[k] += (acc_t)(w * Y[lm_index(l, m)] * sm[m]);
           }
         }
     }
@@ -266,14 +274,14 @@ void oracle_scf_coeffs(const double *x, const double *y, const double *z, const 
       double at = oracle_anl_tilde(n, l);
       for (int m = 0; m <= l; ++m) {
         int k = n * L2 + lm_index(l, m);
-        double sa = 0.0, sb = 0.0;
+        acc_t sa = 0.0, sb = 0.0;
         for (int ch = 0; ch < ORACLE_NCHUNK; ++ch) {
           sa += SA[(size_t)ch * K + k];
           sb += SB[(size_t)ch * K + k];
         }
         double f = (m == 0 ? 1.0 : 2.0) * at;
-        A[k] = f * sa;
-        B[k] = (m == 0) ? 0.0 : f * sb;
+        A[k] = (double)(f * sa);
+        B[k] = (m == 0) ? 0.0 : (double)(f * sb);
       }
     }
   free(SA);
@@ -305,7 +313,7 @@ void oracle_scf_force(const double *x, const double *y, const double *z, int64_t
       double ph = atan2(s.sinph, s.cosph);
       double xi = (r - 1.0) / (r + 1.0);
       /* (2b) sums over the coefficients */
-      double P = 0.0, ar = 0.0, at = 0.0, ap = 0.0;
+      acc_t P = 0.0, ar = 0.0, at = 0.0, ap = 0.0;
       for (int l = 0; l <= lmax; ++l) {
         /* PhiT_nl / r for l >= 1 without dividing by r */
         oracle_gegenbauer(nmax, 2.0 * l + 1.5, xi, c);
@@ -318,19 +326,19 @@ void oracle_scf_force(const double *x, const double *y, const double *z, int64_t
             double f = -A[k] * sm + B[k] * cm;
             double ph_nl = phi[n * (lmax + 1) + l];
             double dph_nl = dphi[n * (lmax + 1) + l];
-            P += ph_nl * Y[lm_index(l, m)] * e;
-            if (!(l == 0 && r == 0.0)) ar -= dph_nl * Y[lm_index(l, m)] * e;
+            P += (acc_t)(ph_nl * Y[lm_index(l, m)] * e);
+            if (!(l == 0 && r == 0.0)) ar -= (acc_t)(dph_nl * Y[lm_index(l, m)] * e);
             if (l >= 1) {
               double por = fr * c[n];
-              at -= por * dY[lm_index(l, m)] * e;
-              ap -= por * mYs[lm_index(l, m)] * f;
+              at -= (acc_t)(por * dY[lm_index(l, m)] * e);
+              ap -= (acc_t)(por * mYs[lm_index(l, m)] * f);
             }
           }
         }
       }
       double gx, gy, gz;
-      to_cart(&s, ar, at, ap, &gx, &gy, &gz);
-      if (pot) pot[i] = P;
+      to_cart(&s, (double)ar, (double)at, (double)ap, &gx, &gy, &gz);
+      if (pot) pot[i] = (double)P;
       if (ax) ax[i] = gx;
       if (ay) ay[i] = gy;
       if (az) az[i] = gz;
@@ -393,18 +401,18 @@ void oracle_mex_force(const double *x, const double *y, const double *z, const d
   int L2 = (lmax + 1) * (lmax + 2) / 2;
   int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(np > 0 ? np : 1));
   oracle_mex_order(x, y, z, np, order);
-  double *P = (double *)calloc((size_t)(np > 0 ? np : 1), sizeof(double));
-  double *AR = (double *)calloc((size_t)(np > 0 ? np : 1), sizeof(double));
-  double *AT = (double *)calloc((size_t)(np > 0 ? np : 1), sizeof(double));
-  double *AP = (double *)calloc((size_t)(np > 0 ? np : 1), sizeof(double));
+  acc_t *P = (acc_t *)calloc((size_t)(np > 0 ? np : 1), sizeof(acc_t));
+  acc_t *AR = (acc_t *)calloc((size_t)(np > 0 ? np : 1), sizeof(acc_t));
+  acc_t *AT = (acc_t *)calloc((size_t)(np > 0 ? np : 1), sizeof(acc_t));
+  acc_t *AP = (acc_t *)calloc((size_t)(np > 0 ? np : 1), sizeof(acc_t));
   double *Y = (double *)malloc(sizeof(double) * (size_t)L2);
   double *dY = (double *)malloc(sizeof(double) * (size_t)L2);
   double *mYs = (double *)malloc(sizeof(double) * (size_t)L2);
-  double *sc = (double *)calloc((size_t)L2, sizeof(double));
-  double *ss = (double *)calloc((size_t)L2, sizeof(double));
+  acc_t *sc = (acc_t *)calloc((size_t)L2, sizeof(acc_t));
+  acc_t *ss = (acc_t *)calloc((size_t)L2, sizeof(acc_t));
   for (int pass = 0; pass < 2; ++pass) { /* 0: inward sums q (forward); 1: outward p (reverse) */
-    memset(sc, 0, sizeof(double) * (size_t)L2);
-    memset(ss, 0, sizeof(double) * (size_t)L2);
+    memset(sc, 0, sizeof(acc_t) * (size_t)L2);
+    memset(ss, 0, sizeof(acc_t) * (size_t)L2);
     for (int64_t k = 0; k < np; ++k) {
       int64_t i = pass == 0 ? order[k] : order[np - 1 - k];
       sph_t s = to_sph(x[i], y[i], z[i]);
@@ -412,7 +420,7 @@ void oracle_mex_force(const double *x, const double *y, const double *z, const d
       double ph = atan2(s.sinph, s.cosph);
       oracle_ylm_deriv(lmax, s.costh, s.sinth, Y, dY, mYs);
       /* field of the running sums at particle i */
-      double Pi = 0.0, ar = 0.0, at = 0.0, ap = 0.0;
+      acc_t Pi = 0.0, ar = 0.0, at = 0.0, ap = 0.0;
       for (int l = 0; l <= lmax; ++l) {
         double g = FOUR_PI / (2.0 * l + 1.0);
         double rad, drad, rado; /* radial factor, its r-derivative, factor / r */
@@ -429,8 +437,8 @@ void oracle_mex_force(const double *x, const double *y, const double *z, const d
         for (int m = 0; m <= l; ++m) {
           double w = (m == 0 ? 1.0 : 2.0) * g;
           double cm = cos(m * ph), sm = sin(m * ph);
-          double e = sc[lm_index(l, m)] * cm + ss[lm_index(l, m)] * sm;
-          double f = -sc[lm_index(l, m)] * sm + ss[lm_index(l, m)] * cm;
+          acc_t e = sc[lm_index(l, m)] * cm + ss[lm_index(l, m)] * sm;
+          acc_t f = -sc[lm_index(l, m)] * sm + ss[lm_index(l, m)] * cm;
           Pi -= w * Y[lm_index(l, m)] * e * rad;
           ar += w * Y[lm_index(l, m)] * e * drad;
           at += w * dY[lm_index(l, m)] * e * rado;
@@ -446,8 +454,8 @@ void oracle_mex_force(const double *x, const double *y, const double *z, const d
       for (int l = 0; l <= lmax; ++l) {
         double rp = (pass == 0) ? pow(r, (double)l) : pow(r, -(l + 1.0));
         for (int m = 0; m <= l; ++m) {
-          sc[lm_index(l, m)] += mass[i] * rp * Y[lm_index(l, m)] * cos(m * ph);
-          ss[lm_index(l, m)] += mass[i] * rp * Y[lm_index(l, m)] * sin(m * ph);
+          sc[lm_index(l, m)] += (acc_t)(mass[i] * rp * Y[lm_index(l, m)] * cos(m * ph));
+          ss[lm_index(l, m)] += (acc_t)(mass[i] * rp * Y[lm_index(l, m)] * sin(m * ph));
         }
       }
     }
@@ -455,8 +463,8 @@ void oracle_mex_force(const double *x, const double *y, const double *z, const d
   for (int64_t i = 0; i < np; ++i) {
     sph_t s = to_sph(x[i], y[i], z[i]);
     double gx, gy, gz;
-    to_cart(&s, AR[i], AT[i], AP[i], &gx, &gy, &gz);
-    if (pot) pot[i] = P[i];
+    to_cart(&s, (double)AR[i], (double)AT[i], (double)AP[i], &gx, &gy, &gz);
+    if (pot) pot[i] = (double)P[i];
     if (ax) ax[i] = gx;
     if (ay) ay[i] = gy;
     if (az) az[i] = gz;
