@@ -112,6 +112,45 @@ def _dev(t, name, dtype=torch.float64):
     return t
 
 
+def _validate(items):
+    """Check every array argument before anything is launched.
+
+    items: (tensor or None, name, count, dtype, exact).  Sizes are checked first
+    (ValueError: a tensor with `exact` must hold exactly `count` elements, otherwise at
+    least `count`), then type, layout and device (TypeError): FP64 (int64 for offsets,
+    any type for the workspace), contiguous, on one GPU.  The library only sees
+    pointers, so a short array here would otherwise become out-of-bounds device
+    accesses."""
+    for t, name, count, _, exact in items:
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name}: expected a torch tensor")
+        k = t.numel() if name != "ws" else t.numel() * t.element_size()
+        if exact and k != count:
+            raise ValueError(f"{name}: {k} elements, expected {count}")
+        if not exact and k < count:
+            what = "bytes" if name == "ws" else "elements"
+            raise ValueError(f"{name}: {k} {what}, at least {count} needed")
+    device = None
+    for t, name, _, dtype, _ in items:
+        if t is None:
+            continue
+        if dtype is None:
+            if not (t.is_cuda and t.is_contiguous()):
+                raise TypeError(f"{name}: expected a contiguous CUDA tensor")
+        else:
+            _dev(t, name, dtype)
+        if device is None:
+            device = t.device
+        elif t.device != device:
+            raise TypeError(f"{name}: on {t.device}, the other arrays are on {device}")
+
+
+def _nbytes(t) -> int:
+    return t.numel() * t.element_size()
+
+
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -160,22 +199,60 @@ def etics_batched_workspace_size(ntotal: int, nsys: int, nmax: int, lmax: int,
     return lib().etics_batched_workspace_size(ntotal, nsys, nmax, lmax, _prec(precision))
 
 
+F64 = torch.float64
+I64 = torch.int64
+
+
+def _outputs(outputs, n, device, pot, ax, ay, az):
+    mk = lambda: torch.empty(n, dtype=F64, device=device)
+    if outputs & ETICS_POT:
+        pot = mk() if pot is None else pot
+    if outputs & ETICS_ACC:
+        ax = mk() if ax is None else ax
+        ay = mk() if ay is None else ay
+        az = mk() if az is None else az
+    return pot, ax, ay, az
+
+
+def _out_items(outputs, n, pot, ax, ay, az):
+    if outputs not in (ETICS_POT, ETICS_ACC, ETICS_POT_ACC):
+        raise ValueError("outputs must be ETICS_POT, ETICS_ACC or ETICS_POT_ACC")
+    items = []
+    if outputs & ETICS_POT:
+        items.append((pot, "pot", n, F64, False))
+    if outputs & ETICS_ACC:
+        items += [(ax, "ax", n, F64, False), (ay, "ay", n, F64, False), (az, "az", n, F64, False)]
+    return items
+
+
+def _coeff_count_checked(nmax: int, lmax: int) -> int:
+    K = etics_coeff_count(nmax, lmax)
+    if K < 0:
+        raise EticsError(-1, "nmax/lmax outside the caps")
+    return K
+
+
+def _first_tensor(x):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError("x: expected a torch tensor")
+    return x.numel(), x.device
+
+
 def etics_scf_coeffs(x, y, z, m, nmax: int, lmax: int, precision=ETICS_MIXED_FP64ACC,
                      A=None, B=None, ws=None, stream=None):
     """SCF coefficients (A, B) of the particles (x, y, z, m)."""
     p = _prec(precision)
-    for t, nm in ((x, "x"), (y, "y"), (z, "z"), (m, "m")):
-        _dev(t, nm)
-    n = x.numel()
-    K = etics_coeff_count(nmax, lmax)
-    if K < 0:
-        raise EticsError(-1, "nmax/lmax outside the caps")
-    A = torch.empty(K, dtype=torch.float64, device=x.device) if A is None else _dev(A, "A")
-    B = torch.empty(K, dtype=torch.float64, device=x.device) if B is None else _dev(B, "B")
+    n, device = _first_tensor(x)
+    K = _coeff_count_checked(nmax, lmax)
     need = etics_scf_workspace_size(n, nmax, lmax, p)
-    ws = workspace(need, x.device) if ws is None else ws
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (m, "m", n, F64, True), (A, "A", K, F64, False), (B, "B", K, F64, False),
+               (ws, "ws", need, None, False)])
+    A = torch.empty(K, dtype=F64, device=device) if A is None else A
+    B = torch.empty(K, dtype=F64, device=device) if B is None else B
+    ws = workspace(need, device) if ws is None else ws
     _check(lib().etics_scf_coeffs(_ptr(x), _ptr(y), _ptr(z), _ptr(m), n, nmax, lmax, p, _ptr(A), _ptr(B),
-                                  _ptr(ws), ws.numel(), _stream(stream)))
+                                  _ptr(ws), _nbytes(ws), _stream(stream)))
     return A, B
 
 
@@ -183,20 +260,18 @@ def etics_scf_force(x, y, z, nmax: int, lmax: int, A, B, precision=ETICS_MIXED_F
                     outputs=ETICS_POT_ACC, pot=None, ax=None, ay=None, az=None, ws=None, stream=None):
     """SCF potential and acceleration at (x, y, z) from coefficients A, B."""
     p = _prec(precision)
-    for t, nm in ((x, "x"), (y, "y"), (z, "z"), (A, "A"), (B, "B")):
-        _dev(t, nm)
-    n = x.numel()
-    mk = lambda: torch.empty(n, dtype=torch.float64, device=x.device)
-    if outputs & ETICS_POT:
-        pot = mk() if pot is None else _dev(pot, "pot")
-    if outputs & ETICS_ACC:
-        ax = mk() if ax is None else _dev(ax, "ax")
-        ay = mk() if ay is None else _dev(ay, "ay")
-        az = mk() if az is None else _dev(az, "az")
+    n, device = _first_tensor(x)
+    K = _coeff_count_checked(nmax, lmax)
     need = etics_scf_workspace_size(n, nmax, lmax, p)
-    ws = workspace(need, x.device) if ws is None else ws
+    if A is None or B is None:
+        raise TypeError("A and B are required")
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (A, "A", K, F64, False), (B, "B", K, F64, False), (ws, "ws", need, None, False)]
+              + _out_items(outputs, n, pot, ax, ay, az))
+    pot, ax, ay, az = _outputs(outputs, n, device, pot, ax, ay, az)
+    ws = workspace(need, device) if ws is None else ws
     _check(lib().etics_scf_force(_ptr(x), _ptr(y), _ptr(z), n, nmax, lmax, _ptr(A), _ptr(B), p, outputs,
-                                 _ptr(pot), _ptr(ax), _ptr(ay), _ptr(az), _ptr(ws), ws.numel(),
+                                 _ptr(pot), _ptr(ax), _ptr(ay), _ptr(az), _ptr(ws), _nbytes(ws),
                                  _stream(stream)))
     return pot, ax, ay, az
 
@@ -205,20 +280,15 @@ def etics_mex_force(x, y, z, m, lmax: int, precision=ETICS_MIXED_FP64ACC, output
                     pot=None, ax=None, ay=None, az=None, ws=None, stream=None):
     """MEX potential and acceleration of every particle from all the others."""
     p = _prec(precision)
-    for t, nm in ((x, "x"), (y, "y"), (z, "z"), (m, "m")):
-        _dev(t, nm)
-    n = x.numel()
-    mk = lambda: torch.empty(n, dtype=torch.float64, device=x.device)
-    if outputs & ETICS_POT:
-        pot = mk() if pot is None else _dev(pot, "pot")
-    if outputs & ETICS_ACC:
-        ax = mk() if ax is None else _dev(ax, "ax")
-        ay = mk() if ay is None else _dev(ay, "ay")
-        az = mk() if az is None else _dev(az, "az")
+    n, device = _first_tensor(x)
     need = etics_mex_workspace_size(n, lmax, p)
-    ws = workspace(need, x.device) if ws is None else ws
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (m, "m", n, F64, True), (ws, "ws", need, None, False)]
+              + _out_items(outputs, n, pot, ax, ay, az))
+    pot, ax, ay, az = _outputs(outputs, n, device, pot, ax, ay, az)
+    ws = workspace(need, device) if ws is None else ws
     _check(lib().etics_mex_force(_ptr(x), _ptr(y), _ptr(z), _ptr(m), n, lmax, p, outputs,
-                                 _ptr(pot), _ptr(ax), _ptr(ay), _ptr(az), _ptr(ws), ws.numel(),
+                                 _ptr(pot), _ptr(ax), _ptr(ay), _ptr(az), _ptr(ws), _nbytes(ws),
                                  _stream(stream)))
     return pot, ax, ay, az
 
@@ -226,34 +296,41 @@ def etics_mex_force(x, y, z, m, lmax: int, precision=ETICS_MIXED_FP64ACC, output
 def etics_direct_force(x, y, z, m, outputs=ETICS_POT_ACC, pot=None, ax=None, ay=None, az=None,
                        stream=None):
     """Unsoftened FP64 direct-summation potential and acceleration (O(n^2))."""
-    for t, nm in ((x, "x"), (y, "y"), (z, "z"), (m, "m")):
-        _dev(t, nm)
-    n = x.numel()
-    mk = lambda: torch.empty(n, dtype=torch.float64, device=x.device)
-    if outputs & ETICS_POT:
-        pot = mk() if pot is None else _dev(pot, "pot")
-    if outputs & ETICS_ACC:
-        ax = mk() if ax is None else _dev(ax, "ax")
-        ay = mk() if ay is None else _dev(ay, "ay")
-        az = mk() if az is None else _dev(az, "az")
+    n, device = _first_tensor(x)
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (m, "m", n, F64, True)] + _out_items(outputs, n, pot, ax, ay, az))
+    pot, ax, ay, az = _outputs(outputs, n, device, pot, ax, ay, az)
     _check(lib().etics_direct_force(_ptr(x), _ptr(y), _ptr(z), _ptr(m), n, outputs, _ptr(pot), _ptr(ax),
                                     _ptr(ay), _ptr(az), _stream(stream)))
     return pot, ax, ay, az
 
 
+def _nsys_of(offsets) -> int:
+    if not isinstance(offsets, torch.Tensor):
+        raise TypeError("offsets: expected a torch tensor")
+    nsys = offsets.numel() - 1
+    if nsys < 1:
+        raise ValueError("offsets: needs nsys + 1 >= 2 entries")
+    return nsys
+
+
 def etics_scf_coeffs_batched(x, y, z, m, offsets, nmax: int, lmax: int, precision=ETICS_MIXED_FP64ACC,
                              A=None, B=None, ws=None, stream=None):
+    """Coefficients of nsys systems stored back to back (offsets: int64 [nsys+1])."""
     p = _prec(precision)
-    _dev(offsets, "offsets", torch.int64)
-    nsys = offsets.numel() - 1
-    n = x.numel()
-    K = etics_coeff_count(nmax, lmax)
-    A = torch.empty(nsys * K, dtype=torch.float64, device=x.device) if A is None else _dev(A, "A")
-    B = torch.empty(nsys * K, dtype=torch.float64, device=x.device) if B is None else _dev(B, "B")
+    n, device = _first_tensor(x)
+    nsys = _nsys_of(offsets)
+    K = _coeff_count_checked(nmax, lmax)
     need = etics_batched_workspace_size(n, nsys, nmax, lmax, p)
-    ws = workspace(need, x.device) if ws is None else ws
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (m, "m", n, F64, True), (offsets, "offsets", nsys + 1, I64, True),
+               (A, "A", nsys * K, F64, False), (B, "B", nsys * K, F64, False),
+               (ws, "ws", need, None, False)])
+    A = torch.empty(nsys * K, dtype=F64, device=device) if A is None else A
+    B = torch.empty(nsys * K, dtype=F64, device=device) if B is None else B
+    ws = workspace(need, device) if ws is None else ws
     _check(lib().etics_scf_coeffs_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(m), _ptr(offsets), nsys, n,
-                                          nmax, lmax, p, _ptr(A), _ptr(B), _ptr(ws), ws.numel(),
+                                          nmax, lmax, p, _ptr(A), _ptr(B), _ptr(ws), _nbytes(ws),
                                           _stream(stream)))
     return A, B
 
@@ -261,24 +338,23 @@ def etics_scf_coeffs_batched(x, y, z, m, offsets, nmax: int, lmax: int, precisio
 def etics_scf_force_batched(x, y, z, offsets, nmax: int, lmax: int, A, B, precision=ETICS_MIXED_FP64ACC,
                             outputs=ETICS_POT_ACC, pot=None, ax=None, ay=None, az=None, ws=None,
                             stream=None):
+    """Potential and acceleration of nsys systems, each from its own coefficients."""
     p = _prec(precision)
-    _dev(offsets, "offsets", torch.int64)
-    nsys = offsets.numel() - 1
-    n = x.numel()
-    for t, nm in ((x, "x"), (y, "y"), (z, "z"), (A, "A"), (B, "B")):
-        _dev(t, nm)
-    mk = lambda: torch.empty(n, dtype=torch.float64, device=x.device)
-    if outputs & ETICS_POT:
-        pot = mk() if pot is None else _dev(pot, "pot")
-    if outputs & ETICS_ACC:
-        ax = mk() if ax is None else _dev(ax, "ax")
-        ay = mk() if ay is None else _dev(ay, "ay")
-        az = mk() if az is None else _dev(az, "az")
+    n, device = _first_tensor(x)
+    nsys = _nsys_of(offsets)
+    K = _coeff_count_checked(nmax, lmax)
     need = etics_batched_workspace_size(n, nsys, nmax, lmax, p)
-    ws = workspace(need, x.device) if ws is None else ws
+    if A is None or B is None:
+        raise TypeError("A and B are required")
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (offsets, "offsets", nsys + 1, I64, True), (A, "A", nsys * K, F64, False),
+               (B, "B", nsys * K, F64, False), (ws, "ws", need, None, False)]
+              + _out_items(outputs, n, pot, ax, ay, az))
+    pot, ax, ay, az = _outputs(outputs, n, device, pot, ax, ay, az)
+    ws = workspace(need, device) if ws is None else ws
     _check(lib().etics_scf_force_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(offsets), nsys, n, nmax, lmax,
                                          _ptr(A), _ptr(B), p, outputs, _ptr(pot), _ptr(ax), _ptr(ay),
-                                         _ptr(az), _ptr(ws), ws.numel(), _stream(stream)))
+                                         _ptr(az), _ptr(ws), _nbytes(ws), _stream(stream)))
     return pot, ax, ay, az
 
 
@@ -287,11 +363,15 @@ def etics_leapfrog_scf_batched(x, y, z, vx, vy, vz, m, offsets, nmax: int, lmax:
                                stream=None):
     """Advance x..vz in place by nsteps KDK steps (one captured graph replayed)."""
     p = _prec(precision)
-    _dev(offsets, "offsets", torch.int64)
-    nsys = offsets.numel() - 1
-    n = x.numel()
+    n, device = _first_tensor(x)
+    nsys = _nsys_of(offsets)
+    _coeff_count_checked(nmax, lmax)
     need = etics_batched_workspace_size(n, nsys, nmax, lmax, p)
-    ws = workspace(need, x.device) if ws is None else ws
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (vx, "vx", n, F64, True), (vy, "vy", n, F64, True), (vz, "vz", n, F64, True),
+               (m, "m", n, F64, True), (offsets, "offsets", nsys + 1, I64, True),
+               (ws, "ws", need, None, False)])
+    ws = workspace(need, device) if ws is None else ws
     _check(lib().etics_leapfrog_scf_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz),
                                             _ptr(m), _ptr(offsets), nsys, n, nmax, lmax, p, float(dt),
-                                            int(nsteps), int(flags), _ptr(ws), ws.numel(), _stream(stream)))
+                                            int(nsteps), int(flags), _ptr(ws), _nbytes(ws), _stream(stream)))

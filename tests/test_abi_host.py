@@ -124,3 +124,78 @@ def test_timing_events_need_both_or_neither(L):
     assert b"timing" in L.etics_last_error()
     assert t(None, ctypes.c_void_p(0x1000)) == -1
     assert t(None, None) == 0  # off: stores nothing, touches no device
+
+
+# ------------------------------------------------ binding: sizes checked before launch
+def _cpu(n, dtype=None):
+    import torch
+    return torch.zeros(n, dtype=torch.float64 if dtype is None else dtype)
+
+
+def test_binding_rejects_mismatched_sizes_before_any_launch():
+    """Every array argument is size-checked on the host (ValueError) before its type or
+    device (TypeError), so these CPU tensors never reach the library."""
+    import torch
+
+    from paper_1406_4254_amd import etics as E
+    n = 100
+    x, y, z, m = _cpu(n), _cpu(n), _cpu(n), _cpu(n)
+    K = E.etics_coeff_count(4, 3)
+    with pytest.raises(ValueError, match="y"):
+        E.etics_scf_coeffs(x, _cpu(n - 1), z, m, 4, 3)
+    with pytest.raises(ValueError, match="m"):
+        E.etics_scf_coeffs(x, y, z, _cpu(n + 1), 4, 3)
+    with pytest.raises(ValueError, match="A"):
+        E.etics_scf_coeffs(x, y, z, m, 4, 3, A=_cpu(K - 1))
+    with pytest.raises(ValueError, match="ws"):
+        E.etics_scf_coeffs(x, y, z, m, 4, 3, ws=torch.zeros(16, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="B"):
+        E.etics_scf_force(x, y, z, 4, 3, _cpu(K), _cpu(K - 2))
+    with pytest.raises(ValueError, match="pot"):
+        E.etics_scf_force(x, y, z, 4, 3, _cpu(K), _cpu(K), outputs=E.ETICS_POT, pot=_cpu(n - 1))
+    with pytest.raises(ValueError, match="az"):
+        E.etics_scf_force(x, y, z, 4, 3, _cpu(K), _cpu(K), outputs=E.ETICS_ACC, ax=_cpu(n), ay=_cpu(n),
+                          az=_cpu(3))
+    with pytest.raises(ValueError, match="outputs"):
+        E.etics_scf_force(x, y, z, 4, 3, _cpu(K), _cpu(K), outputs=0)
+    with pytest.raises(ValueError, match="z"):
+        E.etics_mex_force(x, y, _cpu(n - 1), m, 6)
+    with pytest.raises(ValueError, match="ax"):
+        E.etics_mex_force(x, y, z, m, 6, ax=_cpu(1), ay=_cpu(n), az=_cpu(n))
+    with pytest.raises(ValueError, match="m"):
+        E.etics_direct_force(x, y, z, _cpu(n - 1))
+    off = torch.tensor([0, 40, 100], dtype=torch.int64)
+    with pytest.raises(ValueError, match="A"):
+        E.etics_scf_coeffs_batched(x, y, z, m, off, 4, 3, A=_cpu(K))  # needs nsys * K
+    with pytest.raises(ValueError, match="offsets"):
+        E.etics_scf_coeffs_batched(x, y, z, m, torch.zeros(1, dtype=torch.int64), 4, 3)
+    with pytest.raises(ValueError, match="B"):
+        E.etics_scf_force_batched(x, y, z, off, 4, 3, _cpu(2 * K), _cpu(2 * K - 1))
+    with pytest.raises(ValueError, match="vy"):
+        E.etics_leapfrog_scf_batched(x, y, z, _cpu(n), _cpu(n - 1), _cpu(n), m, off, 4, 3, 0.01, 2)
+    with pytest.raises(ValueError, match="m"):
+        E.etics_leapfrog_scf_batched(x, y, z, _cpu(n), _cpu(n), _cpu(n), _cpu(7), off, 4, 3, 0.01, 2)
+
+
+def test_binding_rejects_host_and_wrong_typed_tensors():
+    import torch
+
+    from paper_1406_4254_amd import etics as E
+    n = 50
+    x, y, z, m = _cpu(n), _cpu(n), _cpu(n), _cpu(n)
+    with pytest.raises(TypeError, match="CUDA"):
+        E.etics_scf_coeffs(x, y, z, m, 4, 3)  # right sizes, but host memory
+    with pytest.raises(TypeError):
+        E.etics_mex_force(x, y, z, _cpu(n, torch.float32), 6)
+    off = torch.tensor([0, 50], dtype=torch.int32)
+    with pytest.raises(TypeError):
+        E.etics_scf_coeffs_batched(x, y, z, m, off, 4, 3)
+    with pytest.raises(TypeError):
+        E.etics_scf_coeffs([0.0], y, z, m, 4, 3)
+    with pytest.raises(EticsErrorType()):
+        E.etics_scf_coeffs(x, y, z, m, 30, 3)  # cutoffs outside the caps
+
+
+def EticsErrorType():
+    from paper_1406_4254_amd import etics as E
+    return E.EticsError
