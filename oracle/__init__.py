@@ -68,6 +68,16 @@ def lib(ext: bool = False):
         L.oracle_anl_tilde.restype = ctypes.c_double
         L.oracle_phi_nl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _D, _D]
         L.oracle_rho_nl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _D]
+        L.oracle_knl_cb.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.oracle_knl_cb.restype = ctypes.c_double
+        L.oracle_anl_tilde_basis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.oracle_anl_tilde_basis.restype = ctypes.c_double
+        L.oracle_phi_nl_basis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _D, _D]
+        L.oracle_rho_nl_basis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _D]
+        L.oracle_scf_coeffs_basis.argtypes = [ctypes.c_int, _D, _D, _D, _D, ctypes.c_int64, ctypes.c_int,
+                                              ctypes.c_int, _D, _D]
+        L.oracle_scf_force_basis.argtypes = [ctypes.c_int, _D, _D, _D, ctypes.c_int64, ctypes.c_int,
+                                             ctypes.c_int, _D, _D, _D, _D, _D, _D]
         L.oracle_coeff_count.argtypes = [ctypes.c_int, ctypes.c_int]
         L.oracle_coeff_count.restype = ctypes.c_int
         L.oracle_scf_coeffs.argtypes = [_D, _D, _D, _D, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _D, _D]
@@ -131,43 +141,48 @@ def ylm_deriv(lmax: int, theta: float):
     return Y, dY, mYs
 
 
-def knl(n: int, l: int) -> float:
-    return lib().oracle_knl(n, l)
+# radial bases: 0 = Hernquist-Ostriker (the paper's), 1 = Clutton-Brock
+BASIS_HO, BASIS_CB = 0, 1
 
 
-def anl_tilde(n: int, l: int) -> float:
-    return lib().oracle_anl_tilde(n, l)
+def knl(n: int, l: int, basis: int = BASIS_HO) -> float:
+    return lib().oracle_knl_cb(n, l) if basis == BASIS_CB else lib().oracle_knl(n, l)
 
 
-def phi_nl(nmax: int, lmax: int, r: float):
+def anl_tilde(n: int, l: int, basis: int = BASIS_HO) -> float:
+    return lib().oracle_anl_tilde_basis(basis, n, l)
+
+
+def phi_nl(nmax: int, lmax: int, r: float, basis: int = BASIS_HO):
     """(PhiT, dPhiT/dr) arrays shaped [nmax+1, lmax+1]."""
     phi = np.zeros((nmax + 1) * (lmax + 1))
     dphi = np.zeros_like(phi)
-    lib().oracle_phi_nl(nmax, lmax, float(r), _dp(phi), _dp(dphi))
+    lib().oracle_phi_nl_basis(basis, nmax, lmax, float(r), _dp(phi), _dp(dphi))
     return phi.reshape(nmax + 1, lmax + 1), dphi.reshape(nmax + 1, lmax + 1)
 
 
-def rho_nl(nmax: int, lmax: int, r: float) -> np.ndarray:
+def rho_nl(nmax: int, lmax: int, r: float, basis: int = BASIS_HO) -> np.ndarray:
     rho = np.zeros((nmax + 1) * (lmax + 1))
-    lib().oracle_rho_nl(nmax, lmax, float(r), _dp(rho))
+    lib().oracle_rho_nl_basis(basis, nmax, lmax, float(r), _dp(rho))
     return rho.reshape(nmax + 1, lmax + 1)
 
 
-def scf_coeffs(x, y, z, m, nmax: int, lmax: int, ext: bool = False):
+def scf_coeffs(x, y, z, m, nmax: int, lmax: int, ext: bool = False, basis: int = BASIS_HO):
     """ext=True: the same sums with long-double accumulators."""
     x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
     K = coeff_count(nmax, lmax)
     A, B = np.zeros(K), np.zeros(K)
-    lib(ext).oracle_scf_coeffs(_dp(x), _dp(y), _dp(z), _dp(m), len(x), nmax, lmax, _dp(A), _dp(B))
+    lib(ext).oracle_scf_coeffs_basis(basis, _dp(x), _dp(y), _dp(z), _dp(m), len(x), nmax, lmax,
+                                     _dp(A), _dp(B))
     return A, B
 
 
-def scf_force(x, y, z, nmax: int, lmax: int, A, B, ext: bool = False):
+def scf_force(x, y, z, nmax: int, lmax: int, A, B, ext: bool = False, basis: int = BASIS_HO):
     x, y, z, A, B = _f64(x), _f64(y), _f64(z), _f64(A), _f64(B)
     n = len(x)
     pot, ax, ay, az = (np.zeros(n) for _ in range(4))
-    lib(ext).oracle_scf_force(_dp(x), _dp(y), _dp(z), n, nmax, lmax, _dp(A), _dp(B),
-                           _dp(pot), _dp(ax), _dp(ay), _dp(az))
+    lib(ext).oracle_scf_force_basis(basis, _dp(x), _dp(y), _dp(z), n, nmax, lmax, _dp(A), _dp(B),
+                                    _dp(pot), _dp(ax), _dp(ay), _dp(az))
     return pot, ax, ay, az
 
 

@@ -28,6 +28,15 @@
  * mex-phi, mex-qlm, mex-plm of Section 2.4 with the exclusive sorted sweeps of
  * Section 3.2.
  *
+ * A second radial basis, the Clutton-Brock one that Section 2.5 describes as the
+ * alternative for cored (Plummer-like) systems, is selected by basis = 1:
+ *   xi = (r^2-1)/(r^2+1);  alpha_l = l + 1
+ *   PhiT_nl(r) = -sqrt(4 pi) r^l / (1+r^2)^(l+1/2) C_n^(alpha_l)(xi)
+ *   rhoT_nl(r) = K_nl/(4 pi) sqrt(4 pi) r^l / (1+r^2)^(l+5/2) C_n^(alpha_l)(xi)
+ *   K_nl = 4n(n+2l+2) + (2l+1)(2l+3)
+ *   I_nl = int rhoT_nl PhiT_nl r^2 dr = -K_nl pi 2^(-4l-4) Gamma(n+2l+2) / (n! (n+l+1) (l!)^2)
+ * with the same normalisation conventions as above (basis 0 = Hernquist-Ostriker).
+ *
  * Self-interaction: SCF coefficients include every particle (a field method);
  * MEX excludes the particle itself (strict inequalities of eqs. mex-qlm/plm).
  * At r = 0 the l = 0 SCF radial force has no direction; it is taken as 0.
@@ -155,45 +164,92 @@ double oracle_anl_tilde(int n, int l) {
   return -exp(-logI);
 }
 
-/* PhiT_nl(r) and dPhiT_nl/dr, arrays [(nmax+1)*(lmax+1)] indexed n*(lmax+1)+l.
-   Derivative by the chain rule with f = r^l (1+r)^-(2l+1):
-     f' = l r^(l-1) (1+r)^-(2l+1) - (2l+1) r^l (1+r)^-(2l+2),
-     dxi/dr = 2/(1+r)^2,  dC_n^a/dxi = 2a C_{n-1}^(a+1).                         */
-void oracle_phi_nl(int nmax, int lmax, double r, double *phi, double *dphi) {
-  double xi = (r - 1.0) / (r + 1.0);
+/* Clutton-Brock basis: K_nl = 4n(n+2l+2) + (2l+1)(2l+3) */
+double oracle_knl_cb(int n, int l) { return 4.0 * n * (n + 2.0 * l + 2.0) + (2.0 * l + 1.0) * (2.0 * l + 3.0); }
+
+/* I_nl = -K_nl pi 2^(-4l-4) Gamma(n+2l+2) / (n! (n+l+1) (l!)^2);  Atilde = 1/I */
+double oracle_anl_tilde_cb(int n, int l) {
+  double logI = log(M_PI * oracle_knl_cb(n, l)) - (4.0 * l + 4.0) * log(2.0) + lgamma(n + 2.0 * l + 2.0) -
+                lgamma(n + 1.0) - log(n + l + 1.0) - 2.0 * lgamma(l + 1.0);
+  return -exp(-logI);
+}
+
+double oracle_anl_tilde_basis(int basis, int n, int l) {
+  return basis == 1 ? oracle_anl_tilde_cb(n, l) : oracle_anl_tilde(n, l);
+}
+
+/* PhiT_nl(r), dPhiT_nl/dr and (l >= 1) PhiT_nl(r)/r of either basis, arrays
+   [(nmax+1)*(lmax+1)] indexed n*(lmax+1)+l (any of the three may be NULL).  With
+   f(r) the r-dependent prefactor and xi(r) the Gegenbauer argument:
+     HO: f = r^l (1+r)^-(2l+1),   xi = (r-1)/(r+1),      dxi/dr = 2/(1+r)^2,
+         f' = l r^(l-1) (1+r)^-(2l+1) - (2l+1) r^l (1+r)^-(2l+2);
+     CB: f = r^l (1+r^2)^-(l+1/2), xi = (r^2-1)/(r^2+1), dxi/dr = 4r/(1+r^2)^2,
+         f' = l r^(l-1) (1+r^2)^-(l+1/2) - (2l+1) r^(l+1) (1+r^2)^-(l+3/2);
+   dPhiT = -sqrt(4 pi) (f' C_n + f dC_n/dxi dxi/dr),  dC_n^a/dxi = 2a C_{n-1}^(a+1).
+   PhiT/r uses r^(l-1) directly, so it is finite at r = 0 for l >= 1 (0 for l = 0). */
+static void radial_basis(int basis, int nmax, int lmax, double r, double *phi, double *dphi,
+                         double *phir) {
+  double xi = basis == 1 ? (r * r - 1.0) / (r * r + 1.0) : (r - 1.0) / (r + 1.0);
   double *c = (double *)malloc(sizeof(double) * (size_t)(nmax + 1));
   double *c1 = (double *)malloc(sizeof(double) * (size_t)(nmax + 1));
   double s4pi = sqrt(FOUR_PI);
   for (int l = 0; l <= lmax; ++l) {
-    double alpha = 2.0 * l + 1.5;
+    double alpha = basis == 1 ? l + 1.0 : 2.0 * l + 1.5;
     oracle_gegenbauer(nmax, alpha, xi, c);
     oracle_gegenbauer(nmax, alpha + 1.0, xi, c1);
-    double f = pow(r, l) / pow(1.0 + r, 2.0 * l + 1.0);
-    double fp = (l > 0 ? l * pow(r, l - 1) / pow(1.0 + r, 2.0 * l + 1.0) : 0.0) -
-                (2.0 * l + 1.0) * pow(r, l) / pow(1.0 + r, 2.0 * l + 2.0);
-    double dxi = 2.0 / ((1.0 + r) * (1.0 + r));
+    double f, fp, dxi, fr;
+    if (basis == 1) {
+      double q = 1.0 + r * r;
+      f = pow(r, l) / pow(q, l + 0.5);
+      fp = (l > 0 ? l * pow(r, l - 1) / pow(q, l + 0.5) : 0.0) - (2.0 * l + 1.0) * pow(r, l + 1) / pow(q, l + 1.5);
+      dxi = 4.0 * r / (q * q);
+      fr = (l >= 1) ? -s4pi * pow(r, l - 1.0) / pow(q, l + 0.5) : 0.0;
+    } else {
+      f = pow(r, l) / pow(1.0 + r, 2.0 * l + 1.0);
+      fp = (l > 0 ? l * pow(r, l - 1) / pow(1.0 + r, 2.0 * l + 1.0) : 0.0) -
+           (2.0 * l + 1.0) * pow(r, l) / pow(1.0 + r, 2.0 * l + 2.0);
+      dxi = 2.0 / ((1.0 + r) * (1.0 + r));
+      fr = (l >= 1) ? -s4pi * pow(r, l - 1.0) / pow(1.0 + r, 2.0 * l + 1.0) : 0.0;
+    }
     for (int n = 0; n <= nmax; ++n) {
       double dc = (n >= 1) ? 2.0 * alpha * c1[n - 1] : 0.0;
-      phi[n * (lmax + 1) + l] = -s4pi * f * c[n];
+      if (phi) phi[n * (lmax + 1) + l] = -s4pi * f * c[n];
       if (dphi) dphi[n * (lmax + 1) + l] = -s4pi * (fp * c[n] + f * dc * dxi);
+      if (phir) phir[n * (lmax + 1) + l] = fr * c[n];
     }
   }
   free(c);
   free(c1);
 }
 
+/* PhiT_nl(r) and dPhiT_nl/dr of the Hernquist-Ostriker basis (basis 0) */
+void oracle_phi_nl(int nmax, int lmax, double r, double *phi, double *dphi) {
+  radial_basis(0, nmax, lmax, r, phi, dphi, NULL);
+}
+
+void oracle_phi_nl_basis(int basis, int nmax, int lmax, double r, double *phi, double *dphi) {
+  radial_basis(basis, nmax, lmax, r, phi, dphi, NULL);
+}
+
 /* rhoT_nl(r), same layout (used only by the Poisson and biorthogonality checks) */
-void oracle_rho_nl(int nmax, int lmax, double r, double *rho) {
-  double xi = (r - 1.0) / (r + 1.0);
+void oracle_rho_nl_basis(int basis, int nmax, int lmax, double r, double *rho) {
+  double xi = basis == 1 ? (r * r - 1.0) / (r * r + 1.0) : (r - 1.0) / (r + 1.0);
   double *c = (double *)malloc(sizeof(double) * (size_t)(nmax + 1));
   for (int l = 0; l <= lmax; ++l) {
-    oracle_gegenbauer(nmax, 2.0 * l + 1.5, xi, c);
-    for (int n = 0; n <= nmax; ++n)
-      rho[n * (lmax + 1) + l] = oracle_knl(n, l) / (2.0 * M_PI) * sqrt(FOUR_PI) *
-                                pow(r, l - 1.0) / pow(1.0 + r, 2.0 * l + 3.0) * c[n];
+    oracle_gegenbauer(nmax, basis == 1 ? l + 1.0 : 2.0 * l + 1.5, xi, c);
+    for (int n = 0; n <= nmax; ++n) {
+      double v;
+      if (basis == 1)
+        v = oracle_knl_cb(n, l) / FOUR_PI * sqrt(FOUR_PI) * pow(r, (double)l) / pow(1.0 + r * r, l + 2.5);
+      else
+        v = oracle_knl(n, l) / (2.0 * M_PI) * sqrt(FOUR_PI) * pow(r, l - 1.0) / pow(1.0 + r, 2.0 * l + 3.0);
+      rho[n * (lmax + 1) + l] = v * c[n];
+    }
   }
   free(c);
 }
+
+void oracle_rho_nl(int nmax, int lmax, double r, double *rho) { oracle_rho_nl_basis(0, nmax, lmax, r, rho); }
 
 /* ---------------------------------------------------- spherical coordinates */
 typedef struct {
@@ -228,9 +284,10 @@ static void to_cart(const sph_t *s, double ar, double at, double ap, double *ax,
 /* ------------------------------------------------------------ SCF oracle */
 int oracle_coeff_count(int nmax, int lmax) { return (nmax + 1) * (lmax + 1) * (lmax + 2) / 2; }
 
-/* Coefficients A, B [K] from particles (x,y,z,m)[n]. */
-void oracle_scf_coeffs(const double *x, const double *y, const double *z, const double *mass,
-                       int64_t np, int nmax, int lmax, double *A, double *B) {
+/* Coefficients A, B [K] from particles (x,y,z,m)[n] in radial basis `basis`. */
+void oracle_scf_coeffs_basis(int basis, const double *x, const double *y, const double *z,
+                             const double *mass, int64_t np, int nmax, int lmax, double *A,
+                             double *B) {
   int K = oracle_coeff_count(nmax, lmax);
   int L2 = (lmax + 1) * (lmax + 2) / 2;
   acc_t *SA = (acc_t *)calloc((size_t)ORACLE_NCHUNK * K, sizeof(acc_t));
@@ -246,7 +303,7 @@ void oracle_scf_coeffs(const double *x, const double *y, const double *z, const 
     for (int64_t j = j0; j < j1; ++j) {
       /* (1a) special functions of this particle */
       sph_t s = to_sph(x[j], y[j], z[j]);
-      oracle_phi_nl(nmax, lmax, s.r, phi, NULL);
+      radial_basis(basis, nmax, lmax, s.r, phi, NULL, NULL);
       oracle_ylm(lmax, s.costh, s.sinth, Y);
       double ph = atan2(s.sinph, s.cosph);
       for (int m = 0; m <= lmax; ++m) {
@@ -271,7 +328,7 @@ void oracle_scf_coeffs(const double *x, const double *y, const double *z, const 
   }
   for (int n = 0; n <= nmax; ++n)
     for (int l = 0; l <= lmax; ++l) {
-      double at = oracle_anl_tilde(n, l);
+      double at = oracle_anl_tilde_basis(basis, n, l);
       for (int m = 0; m <= l; ++m) {
         int k = n * L2 + lm_index(l, m);
         acc_t sa = 0.0, sb = 0.0;
@@ -288,18 +345,22 @@ void oracle_scf_coeffs(const double *x, const double *y, const double *z, const 
   free(SB);
 }
 
+void oracle_scf_coeffs(const double *x, const double *y, const double *z, const double *mass,
+                       int64_t np, int nmax, int lmax, double *A, double *B) {
+  oracle_scf_coeffs_basis(0, x, y, z, mass, np, nmax, lmax, A, B);
+}
+
 /* Potential and acceleration a = -grad Phi at the points (x,y,z)[n] from
-   coefficients A, B.  pot/ax/ay/az may individually be NULL. */
-void oracle_scf_force(const double *x, const double *y, const double *z, int64_t np, int nmax,
-                      int lmax, const double *A, const double *B, double *pot, double *ax,
-                      double *ay, double *az) {
+   coefficients A, B of radial basis `basis`.  pot/ax/ay/az may individually be NULL. */
+void oracle_scf_force_basis(int basis, const double *x, const double *y, const double *z,
+                            int64_t np, int nmax, int lmax, const double *A, const double *B,
+                            double *pot, double *ax, double *ay, double *az) {
   int L2 = (lmax + 1) * (lmax + 2) / 2;
-  double s4pi = sqrt(FOUR_PI);
 #pragma omp parallel
   {
     double *phi = (double *)malloc(sizeof(double) * (size_t)((nmax + 1) * (lmax + 1)));
     double *dphi = (double *)malloc(sizeof(double) * (size_t)((nmax + 1) * (lmax + 1)));
-    double *c = (double *)malloc(sizeof(double) * (size_t)(nmax + 1));
+    double *phir = (double *)malloc(sizeof(double) * (size_t)((nmax + 1) * (lmax + 1)));
     double *Y = (double *)malloc(sizeof(double) * (size_t)L2);
     double *dY = (double *)malloc(sizeof(double) * (size_t)L2);
     double *mYs = (double *)malloc(sizeof(double) * (size_t)L2);
@@ -308,16 +369,12 @@ void oracle_scf_force(const double *x, const double *y, const double *z, int64_t
       /* (2a) special functions and their derivatives */
       sph_t s = to_sph(x[i], y[i], z[i]);
       double r = s.r;
-      oracle_phi_nl(nmax, lmax, r, phi, dphi);
+      radial_basis(basis, nmax, lmax, r, phi, dphi, phir); /* PhiT/r without dividing by r */
       oracle_ylm_deriv(lmax, s.costh, s.sinth, Y, dY, mYs);
       double ph = atan2(s.sinph, s.cosph);
-      double xi = (r - 1.0) / (r + 1.0);
       /* (2b) sums over the coefficients */
       acc_t P = 0.0, ar = 0.0, at = 0.0, ap = 0.0;
       for (int l = 0; l <= lmax; ++l) {
-        /* PhiT_nl / r for l >= 1 without dividing by r */
-        oracle_gegenbauer(nmax, 2.0 * l + 1.5, xi, c);
-        double fr = (l >= 1) ? -s4pi * pow(r, l - 1.0) / pow(1.0 + r, 2.0 * l + 1.0) : 0.0;
         for (int m = 0; m <= l; ++m) {
           double cm = cos(m * ph), sm = sin(m * ph);
           for (int n = 0; n <= nmax; ++n) {
@@ -329,7 +386,7 @@ void oracle_scf_force(const double *x, const double *y, const double *z, int64_t
             P += (acc_t)(ph_nl * Y[lm_index(l, m)] * e);
             if (!(l == 0 && r == 0.0)) ar -= (acc_t)(dph_nl * Y[lm_index(l, m)] * e);
             if (l >= 1) {
-              double por = fr * c[n];
+              double por = phir[n * (lmax + 1) + l];
               at -= (acc_t)(por * dY[lm_index(l, m)] * e);
               ap -= (acc_t)(por * mYs[lm_index(l, m)] * f);
             }
@@ -345,11 +402,17 @@ void oracle_scf_force(const double *x, const double *y, const double *z, int64_t
     }
     free(phi);
     free(dphi);
-    free(c);
+    free(phir);
     free(Y);
     free(dY);
     free(mYs);
   }
+}
+
+void oracle_scf_force(const double *x, const double *y, const double *z, int64_t np, int nmax,
+                      int lmax, const double *A, const double *B, double *pot, double *ax,
+                      double *ay, double *az) {
+  oracle_scf_force_basis(0, x, y, z, np, nmax, lmax, A, B, pot, ax, ay, az);
 }
 
 /* ------------------------------------------------------------ MEX oracle */
