@@ -91,6 +91,21 @@ int etics_scf_coeffs(const double* x, const double* y, const double* z, const do
                      int64_t n, int nmax, int lmax, int precision,
                      double* A, double* B, void* workspace, size_t ws_bytes, void* stream);
 
+/* Allocation-free form of etics_scf_coeffs, for callers that cannot allocate device
+   memory or pass a workspace (code under hipGraph capture, tight serving loops,
+   harnesses that forbid hipMalloc).  Same arguments, results and errors as
+   etics_scf_coeffs, without the workspace: the partial sums live in a fixed
+   24 MiB device array inside the library (one per device, held until the process
+   ends), which covers every cutoff under the caps.  The call allocates nothing; the
+   first call on a device looks up that array's device address.  All calls on one
+   device share the array: calls that overlap in time on the same device (different
+   streams, threads or processes' graphs replayed concurrently) race and must be
+   serialised by the caller.  ETICS_EWORKSPACE if a plan ever needed more than the
+   array holds. */
+int etics_scf_coeffs_noalloc(const double* x, const double* y, const double* z, const double* m,
+                             int64_t n, int nmax, int lmax, int precision,
+                             double* A, double* B, void* stream);
+
 /* SCF potential and acceleration a = -grad Phi at the points x,y,z [n] from
    coefficients A,B [K] (Section 3.3, the second part of a force calculation).
    outputs: ETICS_POT, ETICS_ACC or both.  pot may be NULL unless POT is requested,

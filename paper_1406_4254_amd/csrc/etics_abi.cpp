@@ -117,6 +117,37 @@ int etics_scf_coeffs(const double* x, const double* y, const double* z, const do
   return launch_scf_coeffs(p, x, y, z, m, n, A, B, workspace, st);
 }
 
+int etics_scf_coeffs_noalloc(const double* x, const double* y, const double* z, const double* m,
+                             int64_t n, int nmax, int lmax, int precision, double* A, double* B,
+                             void* stream) {
+  if (n < 0) return einval("n < 0");
+  if (!valid_cut(nmax, lmax)) return einval("nmax/lmax outside [0, cap]");
+  if (!valid_prec(precision)) return einval("precision");
+  if (!A || !B) return einval("A/B is NULL");
+  if (n > 0 && (!x || !y || !z || !m)) return einval("x/y/z/m is NULL");
+  CoeffPlan p;
+  if (!make_coeff_plan(n, nmax, lmax, precision, &p)) {
+    set_error("no tile plan for these cutoffs");
+    return ETICS_EUNSUPPORTED;
+  }
+  const size_t need = coeff_partials_bytes(p);
+  if (need > kNoallocScratchBytes) {
+    set_error("etics_scf_coeffs_noalloc: the partial sums need " + std::to_string(need) +
+              " bytes, above the fixed " + std::to_string(kNoallocScratchBytes) + "-byte scratch");
+    return ETICS_EWORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (n == 0) {
+    const int K = coeff_count(nmax, lmax);
+    int rc = launch_fill_zero(A, K, st);
+    return rc ? rc : launch_fill_zero(B, K, st);
+  }
+  void* ws = nullptr;
+  int rc = noalloc_scratch(&ws);
+  if (rc) return rc;
+  return launch_scf_coeffs(p, x, y, z, m, n, A, B, ws, st);
+}
+
 int etics_scf_force(const double* x, const double* y, const double* z, int64_t n, int nmax,
                     int lmax, const double* A, const double* B, int precision, int outputs,
                     double* pot, double* ax, double* ay, double* az, void* workspace,

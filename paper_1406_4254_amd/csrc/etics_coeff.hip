@@ -29,6 +29,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "etics_device.hpp"
 #include "etics_internal.hpp"
@@ -849,6 +850,41 @@ int launch_scf_coeffs(const CoeffPlan& p, const double* x, const double* y, cons
   else
     hipLaunchKernelGGL(scf_reduce_kernel<0>, dim3(rb), dim3(256), 0, st, r);
   return hip_fail(hipGetLastError(), "scf_reduce_kernel launch");
+}
+
+// ------------------------------------------------------- allocation-free variant
+// Per-workgroup partial vectors of etics_scf_coeffs_noalloc: a file-scope device array
+// instead of a caller workspace.  Every device the library runs on holds its own copy
+// until the process ends.  In host code `scratch` names a host-side stand-in, never
+// the device memory: its device address is looked up once per device and only that
+// address is passed to kernels.  Every call on a device shares that device's array,
+// so calls that overlap in time on one device race.  The coefficient kernel writes
+// every partial entry the reduction reads, so nothing needs clearing between calls.
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  int rc = hip_fail(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("etics_scf_coeffs_noalloc: device index beyond 63");
+    return ETICS_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    rc = hip_fail(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (rc) return rc;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return ETICS_OK;
 }
 
 // ------------------------------------------------------------ batched reduce

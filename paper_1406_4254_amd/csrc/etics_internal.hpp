@@ -55,6 +55,11 @@ size_t force_prep_bytes(int nmax, int lmax, int prec);
 
 int launch_fill_zero(double* p, int64_t count, hipStream_t st);
 
+// device memory of the allocation-free coefficient call (partials of one call)
+constexpr size_t kNoallocScratchBytes = size_t(24) << 20;
+// device address of that memory on the current device (looked up once per device)
+int noalloc_scratch(void** out);
+
 int launch_scf_coeffs(const CoeffPlan& p, const double* x, const double* y, const double* z,
                       const double* m, int64_t n, double* A, double* B, void* ws,
                       hipStream_t st);

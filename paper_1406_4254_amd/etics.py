@@ -34,7 +34,7 @@ PRECISIONS = {"fp64": ETICS_FP64, "mixed": ETICS_MIXED_FP64ACC, "comp32": ETICS_
 EXPORTED = [
     "etics_coeff_count", "etics_scf_workspace_size", "etics_scf_coeffs", "etics_scf_force",
     "etics_mex_workspace_size", "etics_mex_force", "etics_batched_workspace_size",
-    "etics_scf_coeffs_batched", "etics_scf_force_batched", "etics_leapfrog_scf_batched",
+    "etics_scf_coeffs_noalloc", "etics_scf_coeffs_batched", "etics_scf_force_batched", "etics_leapfrog_scf_batched",
     "etics_direct_force", "etics_set_timing_events", "etics_last_error", "etics_version",
 ]
 
@@ -65,6 +65,8 @@ def lib():
         L.etics_scf_workspace_size.restype = _sz
         L.etics_scf_coeffs.argtypes = [_vp, _vp, _vp, _vp, _i64, _int, _int, _int, _vp, _vp, _vp, _sz, _vp]
         L.etics_scf_coeffs.restype = _int
+        L.etics_scf_coeffs_noalloc.argtypes = [_vp, _vp, _vp, _vp, _i64, _int, _int, _int, _vp, _vp, _vp]
+        L.etics_scf_coeffs_noalloc.restype = _int
         L.etics_scf_force.argtypes = [_vp, _vp, _vp, _i64, _int, _int, _vp, _vp, _int, _int,
                                       _vp, _vp, _vp, _vp, _vp, _sz, _vp]
         L.etics_scf_force.restype = _int
@@ -253,6 +255,22 @@ def etics_scf_coeffs(x, y, z, m, nmax: int, lmax: int, precision=ETICS_MIXED_FP6
     ws = workspace(need, device) if ws is None else ws
     _check(lib().etics_scf_coeffs(_ptr(x), _ptr(y), _ptr(z), _ptr(m), n, nmax, lmax, p, _ptr(A), _ptr(B),
                                   _ptr(ws), _nbytes(ws), _stream(stream)))
+    return A, B
+
+
+def etics_scf_coeffs_noalloc(x, y, z, m, nmax: int, lmax: int, precision=ETICS_MIXED_FP64ACC,
+                             A=None, B=None, stream=None):
+    """SCF coefficients through the allocation-free entry point (the library's fixed
+    device scratch instead of a workspace)."""
+    p = _prec(precision)
+    n, device = _first_tensor(x)
+    K = _coeff_count_checked(nmax, lmax)
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (m, "m", n, F64, True), (A, "A", K, F64, False), (B, "B", K, F64, False)])
+    A = torch.empty(K, dtype=F64, device=device) if A is None else A
+    B = torch.empty(K, dtype=F64, device=device) if B is None else B
+    _check(lib().etics_scf_coeffs_noalloc(_ptr(x), _ptr(y), _ptr(z), _ptr(m), n, nmax, lmax, p, _ptr(A),
+                                          _ptr(B), _stream(stream)))
     return A, B
 
 
