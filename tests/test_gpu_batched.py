@@ -47,7 +47,7 @@ def test_batched_coeffs_and_force_match_oracle(E, orc, prec):
     pot, ax, ay, az = E.etics_scf_force_batched(x, y, z, off, nmax, lmax, A, B, prec)
     A, B, pot, ax, ay, az = (t.cpu().numpy() for t in (A, B, pot, ax, ay, az))
     ref = per_system(p, nmax, lmax, orc)
-    ctol = 1e-12 if prec == FP64 else 1e-5
+    ctol = 3e-14 if prec == FP64 else 1e-5
     for s, (rA, rB) in enumerate(ref):
         e = acc.coeff_errors(A[s * K:(s + 1) * K], B[s * K:(s + 1) * K], rA, rB)
         assert e["norm_rel"] < ctol, (s, e)
@@ -56,7 +56,7 @@ def test_batched_coeffs_and_force_match_oracle(E, orc, prec):
         ef = acc.summarize(acc.force_rel_err(ax[b:en], ay[b:en], az[b:en], rx, ry, rz))
         ep = acc.summarize(acc.pot_rel_err(pot[b:en], rp))
         if prec == FP64:
-            assert ef["max"] < 1e-10 and ep["max"] < 1e-12, (s, ef, ep)
+            assert ef["max"] < 1e-13 and ep["max"] < 1e-13, (s, ef, ep)
         else:
             assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4 and ep["p99"] <= 1e-4, (s, ef, ep)
 
@@ -93,7 +93,7 @@ def test_batched_empty_systems(E, orc):
             assert np.all(A[s * K:(s + 1) * K] == 0) and np.all(B[s * K:(s + 1) * K] == 0)
         else:
             rA, rB = orc.scf_coeffs(p.x[b:e], p.y[b:e], p.z[b:e], p.m[b:e], nmax, lmax)
-            assert acc.coeff_errors(A[s * K:(s + 1) * K], B[s * K:(s + 1) * K], rA, rB)["norm_rel"] < 1e-12
+            assert acc.coeff_errors(A[s * K:(s + 1) * K], B[s * K:(s + 1) * K], rA, rB)["norm_rel"] < 3e-14
 
 
 def run_lf(E, p, nmax, lmax, dt, steps, prec, flags=0):
@@ -108,7 +108,7 @@ def test_leapfrog_fp64_matches_oracle(E, orc):
     got = run_lf(E, p, nmax, lmax, dt, steps, FP64)
     ref = orc.leapfrog_scf(p.x, p.y, p.z, p.vx, p.vy, p.vz, p.m, p.offsets, nmax, lmax, dt, steps)
     for g, r in zip(got, ref):
-        np.testing.assert_allclose(g, r, rtol=1e-9, atol=1e-11)
+        np.testing.assert_allclose(g, r, rtol=1e-13, atol=1e-14)
 
 
 def test_leapfrog_mixed_close_to_oracle(E, orc):
@@ -179,4 +179,51 @@ def test_leapfrog_step_counts_and_cache_replacement(E, orc):
         got = run_lf(E, p, nmax, lmax, dt, steps, FP64)
         ref = orc.leapfrog_scf(p.x, p.y, p.z, p.vx, p.vy, p.vz, p.m, p.offsets, nmax, lmax, dt, steps)
         for g, r in zip(got, ref):
-            np.testing.assert_allclose(g, r, rtol=1e-9, atol=1e-11)
+            np.testing.assert_allclose(g, r, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_cfg5_leapfrog_100_steps_sampled(E, orc, prec):
+    """The benchmarked run: all 256 systems (~5.5e6 particles), (8,6), 100 graph-replayed
+    KDK steps of dt = 0.01.  Twelve seeded systems are integrated by the oracle alone and
+    compared with the GPU's final positions and velocities; the relative energy change of
+    each sampled system (kinetic plus half the mass-weighted SCF potential, from the
+    oracle) is printed beside the GPU's."""
+    p = W.make_config(5)
+    nmax, lmax, dt, steps = 8, 6, 0.01, 100
+    got = run_lf(E, p, nmax, lmax, dt, steps, prec)
+    rng = np.random.default_rng(5005)
+    worst = 0.0
+    for s in sorted(rng.choice(256, size=12, replace=False)):
+        b, e = int(p.offsets[s]), int(p.offsets[s + 1])
+        sl = slice(b, e)
+        ref = orc.leapfrog_scf(p.x[sl], p.y[sl], p.z[sl], p.vx[sl], p.vy[sl], p.vz[sl], p.m[sl],
+                               np.array([0, e - b], dtype=np.int64), nmax, lmax, dt, steps)
+        dpos = np.sqrt(sum((g[sl] - r) ** 2 for g, r in zip(got[:3], ref[:3])))
+        rpos = np.sqrt(sum(r ** 2 for r in ref[:3]))
+        dvel = np.sqrt(sum((g[sl] - r) ** 2 for g, r in zip(got[3:], ref[3:])))
+        rvel = np.sqrt(sum(r ** 2 for r in ref[3:]))
+        ep = acc.summarize(dpos / (1.0 + rpos))  # relative, kept finite next to the centre
+        ev = acc.summarize(dvel / (1.0 + rvel))
+
+        def energy(st):
+            A, B = orc.scf_coeffs(st[0], st[1], st[2], p.m[sl], nmax, lmax)
+            pot = orc.scf_force(st[0], st[1], st[2], nmax, lmax, A, B)[0]
+            return 0.5 * np.sum(p.m[sl] * (st[3] ** 2 + st[4] ** 2 + st[5] ** 2)) + 0.5 * np.sum(p.m[sl] * pot)
+
+        e0 = energy((p.x[sl], p.y[sl], p.z[sl], p.vx[sl], p.vy[sl], p.vz[sl]))
+        de_ref = energy(ref) / e0 - 1.0
+        de_gpu = energy([g[sl] for g in got]) / e0 - 1.0
+        print(f"lf prec{prec} sys {s} n={e - b}: pos {ep} vel {ev} dE/E oracle {de_ref:.3e} gpu {de_gpu:.3e}",
+              flush=True)
+        # measured on MI355X: FP64 position/velocity max 8.6e-16 / 2.5e-15; mixed
+        # position median <= 2e-8, max 1.8e-7, velocity median <= 4.4e-8, max 4.5e-7, and
+        # the relative energy change within 1.3e-9 of the oracle's
+        if prec == FP64:
+            assert ep["max"] < 1e-14 and ev["max"] < 3e-14, (s, ep, ev)
+        else:
+            assert ep["median"] < 2e-7 and ep["max"] < 2e-6, (s, ep, ev)
+            assert ev["median"] < 5e-7 and ev["max"] < 5e-6, (s, ep, ev)
+            assert abs(de_gpu - de_ref) < 1.5e-8
+        worst = max(worst, ep["max"])
+    print(f"lf prec{prec}: worst sampled position error {worst:.3e}", flush=True)

@@ -8,6 +8,10 @@ from paper_1406_4254_amd import accuracy as acc  # noqa: E402
 from paper_1406_4254_amd import workloads as W  # noqa: E402
 
 FP64, MIXED, COMP32 = 0, 1, 2
+# FP64 bars against the plain oracle at N <= 10^4: about 10x the largest errors measured
+# on MI355X (median 2.3e-14, p99 4.5e-14, max 4.6e-14 over these tests); the two sides
+# add the same terms in different orders (sequential sweeps vs tiles and lane trees)
+F64_MED, F64_P99, F64_MAX = 2e-13, 5e-13, 5e-13
 
 
 @pytest.fixture(scope="module")
@@ -43,7 +47,7 @@ def test_mex_fp64_matches_oracle(E, orc, lmax):
     p = W.make_config(4, 3001)
     got = gpu_mex(E, p.x, p.y, p.z, p.m, lmax, FP64)
     ref = orc.mex_force(p.x, p.y, p.z, p.m, lmax)
-    check(f"mex fp64 l{lmax}", got, ref, 1e-12, 1e-11, 1e-9)
+    check(f"mex fp64 l{lmax}", got, ref, F64_MED, F64_P99, F64_MAX)
 
 
 @pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 4097, 9000])
@@ -54,7 +58,7 @@ def test_mex_ragged_sizes(E, orc, n):
     if n == 1:  # a lone particle feels nothing
         assert np.all(got[0] == 0.0) and np.all(got[1] == 0.0)
         return
-    check(f"mex ragged n{n}", got, ref, 1e-12, 1e-11, 1e-9)
+    check(f"mex ragged n{n}", got, ref, F64_MED, F64_P99, F64_MAX)
 
 
 @pytest.mark.parametrize("prec", [MIXED, COMP32])
@@ -75,7 +79,7 @@ def test_mex_ties_keep_index_order(E, orc):
     m = np.concatenate([p.m, p.m]) * 0.5
     got = gpu_mex(E, x, y, z, m, 6, FP64)
     ref = orc.mex_force(x, y, z, m, 6)
-    check("mex ties", got, ref, 1e-12, 1e-11, 1e-9)
+    check("mex ties", got, ref, F64_MED, F64_P99, F64_MAX)
 
 
 def test_mex_near_ties_below_key_precision(E, orc):
@@ -97,7 +101,7 @@ def test_mex_near_ties_below_key_precision(E, orc):
     m = np.full(x.size, 1.0 / x.size)
     got = gpu_mex(E, x, y, z, m, 6, FP64)
     ref = orc.mex_force(x, y, z, m, 6)
-    check("mex near ties", got, ref, 1e-12, 1e-11, 1e-9)
+    check("mex near ties", got, ref, F64_MED, F64_P99, F64_MAX)
 
 
 def test_mex_origin_particle(E, orc):
@@ -108,28 +112,51 @@ def test_mex_origin_particle(E, orc):
     got = gpu_mex(E, x, y, z, p.m, 5, FP64)
     ref = orc.mex_force(x, y, z, p.m, 5)
     assert all(np.all(np.isfinite(g)) for g in got)
-    check("mex origin", got, ref, 1e-12, 1e-11, 1e-9)
+    check("mex origin", got, ref, F64_MED, F64_P99, F64_MAX)
 
 
 def test_mex_output_modes(E):
+    """want_pot and want_acc are run-time flags of one kernel: the outputs are identical."""
     p = W.make_config(4, 3000)
-    both = gpu_mex(E, p.x, p.y, p.z, p.m, 6, MIXED, 3)
-    pot = gpu_mex(E, p.x, p.y, p.z, p.m, 6, MIXED, 1)
-    accel = gpu_mex(E, p.x, p.y, p.z, p.m, 6, MIXED, 2)
-    np.testing.assert_allclose(pot[0], both[0], rtol=1e-9)
-    for k in (1, 2, 3):
-        np.testing.assert_allclose(accel[k], both[k], rtol=1e-9, atol=1e-12 * np.max(np.abs(both[k])))
+    for prec in (MIXED, FP64):
+        both = gpu_mex(E, p.x, p.y, p.z, p.m, 6, prec, 3)
+        pot = gpu_mex(E, p.x, p.y, p.z, p.m, 6, prec, 1)
+        accel = gpu_mex(E, p.x, p.y, p.z, p.m, 6, prec, 2)
+        assert pot[1] is None and accel[0] is None
+        assert np.array_equal(pot[0], both[0])
+        for k in (1, 2, 3):
+            assert np.array_equal(accel[k], both[k])
+
+
+def test_mex_bitwise_repeat(E):
+    """The sort, the ordered sums and the synthesis take a fixed order: repeated calls,
+    each with a fresh workspace, give identical bits."""
+    p = W.make_config(4, 70_001)
+    for prec in (FP64, MIXED, COMP32):
+        a = gpu_mex(E, p.x, p.y, p.z, p.m, 10, prec)
+        b = gpu_mex(E, p.x, p.y, p.z, p.m, 10, prec)
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
 
 
 def test_mex_cfg4_full_size(E, orc):
-    """N = 10^6 Plummer + Hernquist mixture at lmax = 10: every particle."""
+    """N = 10^6 Plummer + Hernquist mixture at lmax = 10: every particle.
+
+    FP64 is compared with the oracle built with long-double running sums: the plain
+    oracle sweeps the inward and outward sums sequentially over up to 10^6 particles,
+    and its own rounding (measured here as plain vs long double: median 4.5e-12, max
+    5.9e-12) is far above the GPU's, whose sums run over tiles of 128 and short trees.
+    The GPU against the long-double oracle measured median 1.8e-15, p99 1.1e-14, max
+    1.4e-14; the bars are 10x that."""
     p = W.make_config(4)
     ref = orc.mex_force(p.x, p.y, p.z, p.m, 10)
+    ref_ld = orc.mex_force(p.x, p.y, p.z, p.m, 10, ext=True)
+    rf = acc.summarize(acc.force_rel_err(*ref[1:], *ref_ld[1:]))
+    rpot = acc.summarize(acc.pot_rel_err(ref[0], ref_ld[0]))
+    print(f"mex cfg4 plain oracle vs long double: force {rf} pot {rpot}", flush=True)
     for prec in (MIXED, FP64):
         got = gpu_mex(E, p.x, p.y, p.z, p.m, 10, prec)
         if prec == FP64:
-            # inward/outward sums over 10^6 particles taken in two different orders
-            # (sequential sweep vs tiles + scan): FP64 rounding grows like sqrt(N)
-            check("mex cfg4 fp64", got, ref, 1e-10, 1e-9)
+            check("mex cfg4 fp64 vs long-double oracle", got, ref_ld, 2e-14, 1.1e-13, 1.5e-13)
         else:
             check("mex cfg4 mixed", got, ref, 1e-5, 1e-4)

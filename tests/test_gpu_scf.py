@@ -55,7 +55,8 @@ def test_fp64_coeffs_match_oracle(E, orc, nmax, lmax):
     rA, rB = orc.scf_coeffs(p.x, p.y, p.z, p.m, nmax, lmax)
     e = acc.coeff_errors(A, B, rA, rB)
     print(nmax, lmax, e, flush=True)
-    assert e["norm_rel"] < 1e-12 and e["max_rel_to_max"] < 1e-12
+    # measured at most 3.2e-15 over these cutoffs
+    assert e["norm_rel"] < 3e-14 and e["max_rel_to_max"] < 3e-14
 
 
 @pytest.mark.parametrize("nmax,lmax", [(10, 6), (2, 1), (4, 4), (8, 6), (20, 14)])
@@ -63,10 +64,13 @@ def test_fp64_force_match_oracle(E, orc, nmax, lmax):
     p = W.make_config(2, 2500)
     rA, rB = orc.scf_coeffs(p.x, p.y, p.z, p.m, nmax, lmax)
     pot, ax, ay, az = gpu_force(E, p, nmax, lmax, rA, rB, FP64)
+    pot1 = gpu_force(E, p, nmax, lmax, rA, rB, FP64, outputs=1)[0]
     rp, rx, ry, rz = orc.scf_force(p.x, p.y, p.z, nmax, lmax, rA, rB)
     ef = report(f"fp64 force ({nmax},{lmax})", acc.force_rel_err(ax, ay, az, rx, ry, rz))
     ep = report(f"fp64 pot ({nmax},{lmax})", acc.pot_rel_err(pot, rp))
-    assert ef["max"] < 1e-10 and ep["max"] < 1e-12
+    ep1 = report(f"fp64 pot-only ({nmax},{lmax})", acc.pot_rel_err(pot1, rp))
+    # measured at most 1.1e-14 (force and potential, at (20,14))
+    assert ef["max"] < 1e-13 and ep["max"] < 1e-13 and ep1["max"] < 1e-13
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 129, 4099])
@@ -75,11 +79,11 @@ def test_fp64_ragged_sizes(E, orc, n):
     nmax, lmax = 6, 5
     A, B = gpu_coeffs(E, p, nmax, lmax, FP64)
     rA, rB = orc.scf_coeffs(p.x, p.y, p.z, p.m, nmax, lmax)
-    assert acc.coeff_errors(A, B, rA, rB)["norm_rel"] < 1e-12
+    assert acc.coeff_errors(A, B, rA, rB)["norm_rel"] < 3e-14
     pot, ax, ay, az = gpu_force(E, p, nmax, lmax, A, B, FP64)
     rp, rx, ry, rz = orc.scf_force(p.x, p.y, p.z, nmax, lmax, rA, rB)
-    assert np.max(acc.force_rel_err(ax, ay, az, rx, ry, rz)) < 1e-10
-    assert np.max(acc.pot_rel_err(pot, rp)) < 1e-12
+    assert np.max(acc.force_rel_err(ax, ay, az, rx, ry, rz)) < 1e-13
+    assert np.max(acc.pot_rel_err(pot, rp)) < 1e-13
 
 
 # ---------------------------------------------------------- mixed precision gate
@@ -93,11 +97,14 @@ def test_mixed_force_accuracy(E, orc, prec, cfg, n, nmax, lmax):
     ce = acc.coeff_errors(A, B, rA, rB)
     print(f"cfg{cfg} prec{prec} coeff {ce}", flush=True)
     pot, ax, ay, az = gpu_force(E, p, nmax, lmax, A, B, prec)
+    pot1 = gpu_force(E, p, nmax, lmax, A, B, prec, outputs=1)[0]
     rp, rx, ry, rz = orc.scf_force(p.x, p.y, p.z, nmax, lmax, rA, rB)
     ef = report(f"cfg{cfg} prec{prec} force", acc.force_rel_err(ax, ay, az, rx, ry, rz))
     ep = report(f"cfg{cfg} prec{prec} pot", acc.pot_rel_err(pot, rp))
+    ep1 = report(f"cfg{cfg} prec{prec} pot-only", acc.pot_rel_err(pot1, rp))
     assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4
-    assert ep["median"] <= 1e-5 and ep["p99"] <= 1e-4
+    for e in (ep, ep1):
+        assert e["median"] <= 1e-5 and e["p99"] <= 1e-4
     assert ce["norm_rel"] < 1e-5
 
 
@@ -119,21 +126,44 @@ def test_mixed_small_cutoffs_ragged(E, orc, prec, nmax, lmax):
 
 
 def test_cfg2_full_size(E, orc):
-    """N = 10^6, (10,10), triaxial Hernquist: the benchmark workload, every particle."""
+    """N = 10^6, (10,10), triaxial Hernquist: the benchmark workload, every particle, in
+    both output selections (potential and acceleration; potential only).
+
+    FP64 is compared with the oracle built with long-double running sums, whose result
+    differs from the plain oracle only by the plain oracle's own summation rounding
+    (printed); the mixed mode with the plain oracle against the accuracy gate."""
     p = W.make_config(2)
     rA, rB = orc.scf_coeffs(p.x, p.y, p.z, p.m, 10, 10)
     rp, rx, ry, rz = orc.scf_force(p.x, p.y, p.z, 10, 10, rA, rB)
+    lA, lB = orc.scf_coeffs(p.x, p.y, p.z, p.m, 10, 10, ext=True)
+    lp, lx, ly, lz = orc.scf_force(p.x, p.y, p.z, 10, 10, lA, lB, ext=True)
+    print(f"cfg2 plain oracle vs long double: coeff {acc.coeff_errors(rA, rB, lA, lB)} "
+          f"force {acc.summarize(acc.force_rel_err(rx, ry, rz, lx, ly, lz))} "
+          f"pot {acc.summarize(acc.pot_rel_err(rp, lp))}", flush=True)
     for prec in (MIXED, FP64):
         A, B = gpu_coeffs(E, p, 10, 10, prec)
-        ce = acc.coeff_errors(A, B, rA, rB)
         pot, ax, ay, az = gpu_force(E, p, 10, 10, A, B, prec)
-        ef = report(f"cfg2 full prec{prec} force", acc.force_rel_err(ax, ay, az, rx, ry, rz))
-        ep = report(f"cfg2 full prec{prec} pot", acc.pot_rel_err(pot, rp))
-        print(f"cfg2 full prec{prec} coeff {ce}", flush=True)
+        pot1, nx, _, _ = gpu_force(E, p, 10, 10, A, B, prec, outputs=1)
+        assert nx is None
         if prec == FP64:
-            assert ce["norm_rel"] < 1e-12 and ef["max"] < 1e-9
+            ce = acc.coeff_errors(A, B, lA, lB)
+            print(f"cfg2 full fp64 coeff vs long double {ce}", flush=True)
+            ef = report("cfg2 full fp64 force vs long double", acc.force_rel_err(ax, ay, az, lx, ly, lz))
+            ep = report("cfg2 full fp64 pot vs long double", acc.pot_rel_err(pot, lp))
+            ep1 = report("cfg2 full fp64 pot-only vs long double", acc.pot_rel_err(pot1, lp))
+            # measured: coefficients 3.3e-15 (4.7e-15 max/max), force max 1.8e-15,
+            # potential max 1.3e-15
+            assert ce["norm_rel"] < 3.5e-14 and ce["max_rel_to_max"] < 5e-14
+            assert ef["max"] < 2e-14 and ep["max"] < 2e-14 and ep1["max"] < 2e-14
         else:
+            ce = acc.coeff_errors(A, B, rA, rB)
+            print(f"cfg2 full mixed coeff {ce}", flush=True)
+            ef = report("cfg2 full mixed force", acc.force_rel_err(ax, ay, az, rx, ry, rz))
+            ep = report("cfg2 full mixed pot", acc.pot_rel_err(pot, rp))
+            ep1 = report("cfg2 full mixed pot-only", acc.pot_rel_err(pot1, rp))
             assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4 and ce["norm_rel"] < 1e-5
+            for e in (ep, ep1):
+                assert e["median"] <= 1e-5 and e["p99"] <= 1e-4
 
 
 # ------------------------------------------------------------------ edge cases
@@ -180,8 +210,8 @@ def test_origin_and_axis_points(E, orc):
     nmax, lmax = 6, 6
     rA, rB = orc.scf_coeffs(x, y, z, p.m, nmax, lmax)
     A, B = gpu_coeffs(E, q, nmax, lmax, FP64)
-    assert acc.coeff_errors(A, B, rA, rB)["norm_rel"] < 1e-12
-    for prec, tol in ((FP64, 1e-10), (MIXED, 1e-4)):
+    assert acc.coeff_errors(A, B, rA, rB)["norm_rel"] < 3e-14
+    for prec, tol in ((FP64, 1e-13), (MIXED, 1e-4)):
         pot, ax, ay, az = gpu_force(E, q, nmax, lmax, rA, rB, prec)
         rp, rx, ry, rz = orc.scf_force(x, y, z, nmax, lmax, rA, rB)
         assert np.all(np.isfinite(ax)) and np.all(np.isfinite(pot))
@@ -202,8 +232,8 @@ def test_cfg1_full_size(E, orc):
         pot, ax, ay, az = gpu_force(E, p, 10, 6, A, B, prec)
         ef = report(f"cfg1 full prec{prec} force", acc.force_rel_err(ax, ay, az, rx, ry, rz))
         ep = report(f"cfg1 full prec{prec} pot", acc.pot_rel_err(pot, rp))
-        if prec == FP64:
-            assert ce["norm_rel"] < 1e-12 and ef["max"] < 1e-10 and ep["max"] < 1e-10
+        if prec == FP64:  # measured: force max 3.4e-15, potential max 3.5e-15
+            assert ce["norm_rel"] < 3e-14 and ef["max"] < 5e-14 and ep["max"] < 5e-14
         else:
             assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4 and ep["median"] <= 1e-5 and ep["p99"] <= 1e-4
 
@@ -228,8 +258,8 @@ def test_cfg3_full_size_sampled(E, orc):
         ef = report(f"cfg3 sampled prec{prec} force", acc.force_rel_err(ax, ay, az, rx, ry, rz))
         ep = report(f"cfg3 sampled prec{prec} pot", acc.pot_rel_err(pot, rp))
         print(f"cfg3 prec{prec} coeff {ce}", flush=True)
-        if prec == FP64:
-            assert ce["norm_rel"] < 1e-11 and ef["max"] < 1e-8 and ep["max"] < 1e-10
+        if prec == FP64:  # measured: coefficients 1.4e-14, force max 1.5e-14, pot max 1.2e-14
+            assert ce["norm_rel"] < 1.5e-13 and ef["max"] < 1.5e-13 and ep["max"] < 1.5e-13
         else:
             assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4 and ep["median"] <= 1e-5 and ep["p99"] <= 1e-4
         del pot, ax, ay, az
