@@ -57,6 +57,10 @@ extern "C" {
 #define ETICS_MIXED_FP64ACC 1 /* FP32 basis and synthesis, FP64 coefficient reduction */
 #define ETICS_MIXED_COMP32 2  /* FP32 basis and synthesis, compensated (double-float) FP32 reduction */
 
+/* radial bases of the SCF expansion (Section 2.5) */
+#define ETICS_BASIS_HO 0  /* Hernquist-Ostriker: Hernquist model as zeroth order (the paper's) */
+#define ETICS_BASIS_CB 1  /* Clutton-Brock: Plummer model as zeroth order */
+
 /* outputs of the force calls (bit mask) */
 #define ETICS_POT 1
 #define ETICS_ACC 2
@@ -116,6 +120,24 @@ int etics_scf_force(const double* x, const double* y, const double* z, int64_t n
                     int outputs, double* pot, double* ax, double* ay, double* az,
                     void* workspace, size_t ws_bytes, void* stream);
 
+/* The same two calls in either radial basis of Section 2.5 (the calls above use
+   ETICS_BASIS_HO).  ETICS_BASIS_CB is the Clutton-Brock basis, whose zeroth order is a
+   Plummer sphere of scale 1:
+     PhiT_nl(r) = -sqrt(4 pi) r^l (1+r^2)^-(l+1/2) C_n^(l+1)(xi),  xi = (r^2-1)/(r^2+1),
+     rhoT_nl(r) = K_nl/(4 pi) sqrt(4 pi) r^l (1+r^2)^-(l+5/2) C_n^(l+1)(xi),
+     K_nl = 4n(n+2l+2) + (2l+1)(2l+3),
+   normalised and laid out as above (A, B include (2 - delta_m0) and 1/I_nl,
+   I_nl = integral of rhoT_nl PhiT_nl r^2 dr).  Coefficients must be synthesised in the
+   basis they were computed in.  Workspace sizes are those of etics_scf_workspace_size.
+   ETICS_EINVAL for any other basis value. */
+int etics_scf_coeffs_basis(const double* x, const double* y, const double* z, const double* m,
+                           int64_t n, int nmax, int lmax, int precision, int basis,
+                           double* A, double* B, void* workspace, size_t ws_bytes, void* stream);
+int etics_scf_force_basis(const double* x, const double* y, const double* z, int64_t n,
+                          int nmax, int lmax, const double* A, const double* B, int precision,
+                          int basis, int outputs, double* pot, double* ax, double* ay, double* az,
+                          void* workspace, size_t ws_bytes, void* stream);
+
 /* Workspace bytes needed by etics_mex_force; 0 if the arguments are invalid. */
 size_t etics_mex_workspace_size(int64_t n, int lmax, int precision);
 
@@ -143,6 +165,50 @@ int etics_mex_force(const double* x, const double* y, const double* z, const dou
 int etics_direct_force(const double* x, const double* y, const double* z, const double* m,
                        int64_t n, int outputs, double* pot, double* ax, double* ay, double* az,
                        void* stream);
+
+/* ---- Jerk (time derivative of the acceleration) and the fourth-order Hermite
+   integrator.  The paper notes that Hernquist's SCF code computes the jerk (Section
+   3.4) for its fourth-order Hermite scheme, the integrator it names as the next step
+   for SCF (Section 5.4).  Here the particles move with velocities vx,vy,vz, and
+     dA_nlm/dt = (2 - delta_m0) Atilde_nl sum_k m_k d/dt[PhiT_nl Ybar_lm cos(m phi)](x_k(t)),
+   dB/dt likewise with sin, along x_k(t) = x_k + v_k t at t = 0; the jerk of a point i is
+   the total derivative j_i = d/dt a(x_i + v_i t; A(t), B(t)), the field point and every
+   particle of the field moving.  Hernquist-Ostriker basis.  A point exactly on the z
+   axis (x = y = 0) gets a finite jerk in which the azimuthal rotation of the point is
+   not followed (its azimuth has no time derivative there); use positions off the axis
+   where the jerk matters. */
+
+/* dA/dt and dB/dt [K] of particles x,y,z,vx,vy,vz,m [n] (layout and scaling as A, B;
+   fixed summation order, bitwise repeatable).  Workspace: etics_scf_workspace_size. */
+int etics_scf_coeffs_dot(const double* x, const double* y, const double* z, const double* vx,
+                         const double* vy, const double* vz, const double* m, int64_t n, int nmax,
+                         int lmax, int precision, double* Adot, double* Bdot, void* workspace,
+                         size_t ws_bytes, void* stream);
+
+/* Acceleration a = -grad Phi and jerk j = da/dt at the points x,y,z moving with
+   vx,vy,vz [n], from A, B [K] and their time derivatives Adot, Bdot [K].  All six
+   outputs [n] are required.  Workspace: etics_scf_workspace_size. */
+int etics_scf_jerk(const double* x, const double* y, const double* z, const double* vx,
+                   const double* vy, const double* vz, int64_t n, int nmax, int lmax, const double* A,
+                   const double* B, const double* Adot, const double* Bdot, int precision, double* ax,
+                   double* ay, double* az, double* jx, double* jy, double* jz, void* workspace,
+                   size_t ws_bytes, void* stream);
+
+/* Workspace bytes for etics_hermite_scf_batched; 0 if the arguments are invalid. */
+size_t etics_hermite_workspace_size(int64_t ntotal, int nsys, int nmax, int lmax, int precision);
+
+/* nsteps fourth-order Hermite predictor-corrector steps of dt (Makino & Aarseth 1992)
+   for nsys independent systems (offsets, m as for the batched calls), each in its own
+   SCF field:  x_p = x + v dt + a dt^2/2 + j dt^3/6,  v_p = v + a dt + j dt^2/2;
+   a_1, j_1 at (x_p, v_p);  v_1 = v + (a + a_1) dt/2 + (j - j_1) dt^2/12;
+   x_1 = x + (v + v_1) dt/2 + (a - a_1) dt^2/12.  x..vz are updated in place.  Every
+   call first evaluates a, j at the current state.  Graph capture and replay as for
+   etics_leapfrog_scf_batched (ETICS_LEAPFROG_EAGER launches every step directly;
+   the graph cache is its own). */
+int etics_hermite_scf_batched(double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                              const double* m, const int64_t* offsets, int nsys, int64_t ntotal,
+                              int nmax, int lmax, int precision, double dt, int nsteps, int flags,
+                              void* workspace, size_t ws_bytes, void* stream);
 
 /* Workspace bytes for the batched SCF calls and the batched leapfrog over nsys
    systems with ntotal particles in all; 0 if the arguments are invalid. */
@@ -198,6 +264,43 @@ int etics_leapfrog_scf_batched(double* x, double* y, double* z, double* vx, doub
    turns it off; exactly one NULL is ETICS_EINVAL.  The library does not own the
    events and keeps only their handles. */
 int etics_set_timing_events(void* before, void* after);
+
+/* ---- Tile plans and the autotuner (the library's own tuning; no passage of the
+   paper).  A coefficient call takes its tile shape from a plan: nw (wavefronts that
+   share the basis work of a group of 64 particles: 4, 2 or 1, so a tile holds up to 64,
+   128 or 256 particles), tp (particles per tile), streams (copies of the register
+   blocks merged at the end), grid_mult (workgroups per CU, 1 or 2) and, for
+   batched systems, unit (particles per work unit) and split (force workgroups per
+   unit).  Fixed rules give a plan for every cutoff; plans measured faster by the
+   project's tuner (paper_1406_4254_amd/tune.py) are kept in a table keyed by
+   (batched, nmax, lmax, precision, basis) and the particle count tuned at, and used
+   for calls within a factor of 8 of that count.  Every tuned value is checked against
+   the kernel's limits; an invalid one falls back to the fixed rules.  The table is
+   read on first use from $ETICS_TUNING_FILE, else from etics_tuning.json next to
+   libetics.so (if present).  Workspace sizes follow the plan in force when they are
+   queried: change the table before sizing workspaces.  The table is process-wide and
+   guarded by a lock. */
+
+/* Replace the table with the plans of a JSON file ({"plans": [{"batched": 0, "nmax": ..,
+   "lmax": .., "prec": .., "basis": .., "n": .., "nw": .., "tp": .., "streams": ..,
+   "grid_mult": .., "unit": .., "split": ..}, ...]}; a missing or 0 parameter keeps the
+   fixed rule's value).  Returns the number of plans read, or ETICS_EINVAL if the file
+   cannot be read or parsed (the table is then unchanged). */
+int etics_tuning_load(const char* path);
+
+/* Add or replace one plan; params = {nw, tp, streams, grid_mult, unit, split}
+   (nparams = 6; 0 keeps the fixed rule's value). */
+int etics_tuning_set(int batched, int nmax, int lmax, int precision, int basis, int64_t n,
+                     const int* params, int nparams);
+
+/* Empty the table (fixed rules only); the file is not read afterwards. */
+int etics_tuning_clear(void);
+
+/* The plan a coefficient call over n particles would use (batched: n = ntotal, basis
+   ETICS_BASIS_HO): out[0..7] = {nw, tp, streams, grid_mult, unit, split, tuned (0/1),
+   workgroups of a single-system launch}.  nout >= 8. */
+int etics_plan_info(int batched, int64_t n, int nmax, int lmax, int precision, int basis, int* out,
+                    int nout);
 
 /* Message describing the last non-zero return on the calling thread ("" if none). */
 const char* etics_last_error(void);

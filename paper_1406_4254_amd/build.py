@@ -17,8 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libetics.so")
 
-SOURCES = ["etics_coeff.hip", "etics_force.hip", "etics_mex.hip", "etics_batched.hip", "etics_direct.hip",
-           "etics_abi.cpp"]
+SOURCES = ["etics_coeff.hip", "etics_coeff_dot.hip", "etics_force.hip", "etics_jerk.hip", "etics_mex.hip",
+           "etics_batched.hip", "etics_direct.hip", "etics_abi.cpp", "etics_tune.cpp"]
 ARCH = os.environ.get("ETICS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -51,7 +51,7 @@ def build() -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-ldl", "-o", tmp]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

@@ -53,11 +53,18 @@ static bool valid_cut(int nmax, int lmax) {
 static const size_t kAlign = 256;
 
 size_t scf_ws_bytes(int64_t n, int nmax, int lmax, int prec) {
-  CoeffPlan p;
-  if (!make_coeff_plan(n, nmax, lmax, prec, &p)) return 0;
-  size_t a = align_up(coeff_partials_bytes(p), kAlign);
-  size_t b = align_up(force_prep_bytes(nmax, lmax, prec), kAlign);
-  return a > b ? a : b;
+  // the largest partials over both bases (their plans may be tuned differently) and the
+  // time-derivative sums, or the prepared coefficients of the force and jerk passes
+  CoeffPlan p, q, d;
+  if (!make_coeff_plan(n, nmax, lmax, prec, &p, kBasisHO) ||
+      !make_coeff_plan(n, nmax, lmax, prec, &q, kBasisCB) || !dot_plan(p, n, &d))
+    return 0;
+  size_t need = coeff_partials_bytes(p);
+  if (coeff_partials_bytes(q) > need) need = coeff_partials_bytes(q);
+  if (coeff_partials_bytes(d) > need) need = coeff_partials_bytes(d);
+  if (force_prep_bytes(nmax, lmax, prec) > need) need = force_prep_bytes(nmax, lmax, prec);
+  if (jerk_prep_bytes(nmax, lmax, prec) > need) need = jerk_prep_bytes(nmax, lmax, prec);
+  return align_up(need, kAlign);
 }
 
 }  // namespace etics
@@ -79,6 +86,22 @@ int etics_set_timing_events(void* before, void* after) {
   return ETICS_OK;
 }
 
+int etics_plan_info(int batched, int64_t n, int nmax, int lmax, int precision, int basis, int* out,
+                    int nout) {
+  if (n < 0 || !valid_cut(nmax, lmax) || !valid_prec(precision)) return einval("n, cutoffs or precision");
+  if (basis != ETICS_BASIS_HO && basis != ETICS_BASIS_CB) return einval("basis");
+  if ((batched != 0 && batched != 1) || (batched && basis != ETICS_BASIS_HO)) return einval("batched");
+  if (!out || nout < 8) return einval("out needs 8 entries");
+  CoeffPlan p;
+  if (!make_coeff_plan(n, nmax, lmax, precision, &p, basis, batched != 0)) {
+    set_error("no tile plan for these cutoffs");
+    return ETICS_EUNSUPPORTED;
+  }
+  const int v[8] = {p.nw, p.tp, p.streams, p.grid_mult, p.unit, p.split, p.tuned ? 1 : 0, p.grid};
+  for (int i = 0; i < 8; ++i) out[i] = v[i];
+  return ETICS_OK;
+}
+
 const char* etics_last_error(void) { return g_last_error.c_str(); }
 
 const char* etics_version(void) { return "etics-mi355x 0.1 (gfx950)"; }
@@ -88,12 +111,13 @@ size_t etics_scf_workspace_size(int64_t n, int nmax, int lmax, int precision) {
   return scf_ws_bytes(n, nmax, lmax, precision);
 }
 
-int etics_scf_coeffs(const double* x, const double* y, const double* z, const double* m,
-                     int64_t n, int nmax, int lmax, int precision, double* A, double* B,
-                     void* workspace, size_t ws_bytes, void* stream) {
+static int scf_coeffs_impl(const double* x, const double* y, const double* z, const double* m,
+                           int64_t n, int nmax, int lmax, int precision, int basis, double* A,
+                           double* B, void* workspace, size_t ws_bytes, void* stream) {
   if (n < 0) return einval("n < 0");
   if (!valid_cut(nmax, lmax)) return einval("nmax/lmax outside [0, cap]");
   if (!valid_prec(precision)) return einval("precision");
+  if (basis != ETICS_BASIS_HO && basis != ETICS_BASIS_CB) return einval("basis");
   if (!A || !B) return einval("A/B is NULL");
   if (n > 0 && (!x || !y || !z || !m)) return einval("x/y/z/m is NULL");
   const size_t need = scf_ws_bytes(n, nmax, lmax, precision);
@@ -113,8 +137,22 @@ int etics_scf_coeffs(const double* x, const double* y, const double* z, const do
     return rc ? rc : launch_fill_zero(B, K, st);
   }
   CoeffPlan p;
-  make_coeff_plan(n, nmax, lmax, precision, &p);
+  make_coeff_plan(n, nmax, lmax, precision, &p, basis);
   return launch_scf_coeffs(p, x, y, z, m, n, A, B, workspace, st);
+}
+
+int etics_scf_coeffs(const double* x, const double* y, const double* z, const double* m,
+                     int64_t n, int nmax, int lmax, int precision, double* A, double* B,
+                     void* workspace, size_t ws_bytes, void* stream) {
+  return scf_coeffs_impl(x, y, z, m, n, nmax, lmax, precision, ETICS_BASIS_HO, A, B, workspace,
+                         ws_bytes, stream);
+}
+
+int etics_scf_coeffs_basis(const double* x, const double* y, const double* z, const double* m,
+                           int64_t n, int nmax, int lmax, int precision, int basis, double* A,
+                           double* B, void* workspace, size_t ws_bytes, void* stream) {
+  return scf_coeffs_impl(x, y, z, m, n, nmax, lmax, precision, basis, A, B, workspace, ws_bytes,
+                         stream);
 }
 
 int etics_scf_coeffs_noalloc(const double* x, const double* y, const double* z, const double* m,
@@ -148,14 +186,15 @@ int etics_scf_coeffs_noalloc(const double* x, const double* y, const double* z, 
   return launch_scf_coeffs(p, x, y, z, m, n, A, B, ws, st);
 }
 
-int etics_scf_force(const double* x, const double* y, const double* z, int64_t n, int nmax,
-                    int lmax, const double* A, const double* B, int precision, int outputs,
-                    double* pot, double* ax, double* ay, double* az, void* workspace,
-                    size_t ws_bytes, void* stream) {
+static int scf_force_impl(const double* x, const double* y, const double* z, int64_t n, int nmax,
+                          int lmax, const double* A, const double* B, int precision, int basis,
+                          int outputs, double* pot, double* ax, double* ay, double* az,
+                          void* workspace, size_t ws_bytes, void* stream) {
   if (n < 0) return einval("n < 0");
   if (!valid_cut(nmax, lmax)) return einval("nmax/lmax outside [0, cap]");
   if (!valid_prec(precision)) return einval("precision");
   if (outputs < 1 || outputs > 3) return einval("outputs");
+  if (basis != ETICS_BASIS_HO && basis != ETICS_BASIS_CB) return einval("basis");
   if (!A || !B) return einval("A/B is NULL");
   if (n > 0 && (!x || !y || !z)) return einval("x/y/z is NULL");
   if (n > 0 && (outputs & ETICS_POT) && !pot) return einval("pot is NULL");
@@ -172,7 +211,77 @@ int etics_scf_force(const double* x, const double* y, const double* z, int64_t n
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return einval("workspace not 256-byte aligned");
   if (n == 0) return ETICS_OK;
   return launch_scf_force(x, y, z, n, nmax, lmax, A, B, precision, outputs, pot, ax, ay, az,
-                          workspace, reinterpret_cast<hipStream_t>(stream));
+                          workspace, reinterpret_cast<hipStream_t>(stream), basis);
+}
+
+int etics_scf_force(const double* x, const double* y, const double* z, int64_t n, int nmax,
+                    int lmax, const double* A, const double* B, int precision, int outputs,
+                    double* pot, double* ax, double* ay, double* az, void* workspace,
+                    size_t ws_bytes, void* stream) {
+  return scf_force_impl(x, y, z, n, nmax, lmax, A, B, precision, ETICS_BASIS_HO, outputs, pot, ax,
+                        ay, az, workspace, ws_bytes, stream);
+}
+
+int etics_scf_force_basis(const double* x, const double* y, const double* z, int64_t n, int nmax,
+                          int lmax, const double* A, const double* B, int precision, int basis,
+                          int outputs, double* pot, double* ax, double* ay, double* az,
+                          void* workspace, size_t ws_bytes, void* stream) {
+  return scf_force_impl(x, y, z, n, nmax, lmax, A, B, precision, basis, outputs, pot, ax, ay, az,
+                        workspace, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------- jerk
+static int check_ws(void* workspace, size_t ws_bytes, size_t need) {
+  if (need == 0) {
+    set_error("no tile plan for these cutoffs");
+    return ETICS_EUNSUPPORTED;
+  }
+  if (!workspace || ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return ETICS_EWORKSPACE;
+  }
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return einval("workspace not 256-byte aligned");
+  return ETICS_OK;
+}
+
+int etics_scf_coeffs_dot(const double* x, const double* y, const double* z, const double* vx,
+                         const double* vy, const double* vz, const double* m, int64_t n, int nmax,
+                         int lmax, int precision, double* Adot, double* Bdot, void* workspace,
+                         size_t ws_bytes, void* stream) {
+  if (n < 0) return einval("n < 0");
+  if (!valid_cut(nmax, lmax)) return einval("nmax/lmax outside [0, cap]");
+  if (!valid_prec(precision)) return einval("precision");
+  if (!Adot || !Bdot) return einval("Adot/Bdot is NULL");
+  if (n > 0 && (!x || !y || !z || !vx || !vy || !vz || !m)) return einval("x/y/z/vx/vy/vz/m is NULL");
+  int rc = check_ws(workspace, ws_bytes, scf_ws_bytes(n, nmax, lmax, precision));
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (n == 0) {
+    const int K = coeff_count(nmax, lmax);
+    rc = launch_fill_zero(Adot, K, st);
+    return rc ? rc : launch_fill_zero(Bdot, K, st);
+  }
+  CoeffPlan p;
+  make_coeff_plan(n, nmax, lmax, precision, &p);
+  return launch_scf_coeffs_dot(p, x, y, z, vx, vy, vz, m, n, Adot, Bdot, workspace, st);
+}
+
+int etics_scf_jerk(const double* x, const double* y, const double* z, const double* vx,
+                   const double* vy, const double* vz, int64_t n, int nmax, int lmax, const double* A,
+                   const double* B, const double* Adot, const double* Bdot, int precision, double* ax,
+                   double* ay, double* az, double* jx, double* jy, double* jz, void* workspace,
+                   size_t ws_bytes, void* stream) {
+  if (n < 0) return einval("n < 0");
+  if (!valid_cut(nmax, lmax)) return einval("nmax/lmax outside [0, cap]");
+  if (!valid_prec(precision)) return einval("precision");
+  if (!A || !B || !Adot || !Bdot) return einval("A/B/Adot/Bdot is NULL");
+  if (n > 0 && (!x || !y || !z || !vx || !vy || !vz)) return einval("x/y/z/vx/vy/vz is NULL");
+  if (n > 0 && (!ax || !ay || !az || !jx || !jy || !jz)) return einval("ax/ay/az/jx/jy/jz is NULL");
+  int rc = check_ws(workspace, ws_bytes, scf_ws_bytes(n, nmax, lmax, precision));
+  if (rc) return rc;
+  if (n == 0) return ETICS_OK;
+  return launch_scf_jerk(x, y, z, vx, vy, vz, n, nmax, lmax, A, B, Adot, Bdot, precision, ax, ay, az, jx,
+                         jy, jz, workspace, reinterpret_cast<hipStream_t>(stream));
 }
 
 size_t etics_mex_workspace_size(int64_t n, int lmax, int precision) {
@@ -227,7 +336,7 @@ static int check_batched(int64_t ntotal, int nsys, int nmax, int lmax, int prec,
   if (!valid_cut(nmax, lmax)) return einval("nmax/lmax outside [0, cap]");
   if (!valid_prec(prec)) return einval("precision");
   if (!offsets) return einval("offsets is NULL");
-  if (ntotal / kUnitParticles + nsys > INT32_MAX / 2) {
+  if (ntotal / kMinUnitParticles + nsys > INT32_MAX / 2) {
     set_error("too many particles or systems for 32-bit unit indices");
     return ETICS_EUNSUPPORTED;
   }
@@ -236,8 +345,9 @@ static int check_batched(int64_t ntotal, int nsys, int nmax, int lmax, int prec,
 
 size_t etics_batched_workspace_size(int64_t ntotal, int nsys, int nmax, int lmax, int precision) {
   if (ntotal < 0 || nsys < 1 || !valid_cut(nmax, lmax) || !valid_prec(precision)) return 0;
-  if (ntotal / kUnitParticles + nsys > INT32_MAX / 2) return 0;
-  return batched_layout(ntotal, nsys, nmax, lmax, precision).total;
+  if (ntotal / kMinUnitParticles + nsys > INT32_MAX / 2) return 0;
+  const BatchedLayout L = batched_layout(ntotal, nsys, nmax, lmax, precision);
+  return L.ok ? L.total : 0;
 }
 
 int etics_scf_coeffs_batched(const double* x, const double* y, const double* z, const double* m,
@@ -249,23 +359,22 @@ int etics_scf_coeffs_batched(const double* x, const double* y, const double* z, 
   if (!A || !B) return einval("A/B is NULL");
   if (ntotal > 0 && (!x || !y || !z || !m)) return einval("x/y/z/m is NULL");
   const BatchedLayout L = batched_layout(ntotal, nsys, nmax, lmax, precision);
+  if (!L.ok) {
+    set_error("no tile plan for these cutoffs");
+    return ETICS_EUNSUPPORTED;
+  }
   if (!workspace || ws_bytes < L.total) {
     set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
     return ETICS_EWORKSPACE;
   }
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return einval("workspace not 256-byte aligned");
-  CoeffPlan plan;
-  if (!make_coeff_plan(kUnitParticles, nmax, lmax, precision, &plan)) {
-    set_error("no tile plan for these cutoffs");
-    return ETICS_EUNSUPPORTED;
-  }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* base = reinterpret_cast<char*>(workspace);
   int* ustart = reinterpret_cast<int*>(base + L.off_ustart);
   int* usys = reinterpret_cast<int*>(base + L.off_usys);
-  rc = launch_units(offsets, nsys, ntotal, ustart, usys, st);
+  rc = launch_units(offsets, nsys, ntotal, L.plan.unit, ustart, usys, st);
   if (rc) return rc;
-  return launch_scf_coeffs_batched(plan, x, y, z, m, offsets, ustart, usys, nsys, ntotal, A, B,
+  return launch_scf_coeffs_batched(L.plan, x, y, z, m, offsets, ustart, usys, nsys, ntotal, A, B,
                                    base + L.off_partials, st);
 }
 
@@ -282,6 +391,10 @@ int etics_scf_force_batched(const double* x, const double* y, const double* z,
   if (ntotal > 0 && (outputs & ETICS_POT) && !pot) return einval("pot is NULL");
   if (ntotal > 0 && (outputs & ETICS_ACC) && (!ax || !ay || !az)) return einval("ax/ay/az is NULL");
   const BatchedLayout L = batched_layout(ntotal, nsys, nmax, lmax, precision);
+  if (!L.ok) {
+    set_error("no tile plan for these cutoffs");
+    return ETICS_EUNSUPPORTED;
+  }
   if (!workspace || ws_bytes < L.total) {
     set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
     return ETICS_EWORKSPACE;
@@ -291,10 +404,32 @@ int etics_scf_force_batched(const double* x, const double* y, const double* z,
   char* base = reinterpret_cast<char*>(workspace);
   int* ustart = reinterpret_cast<int*>(base + L.off_ustart);
   int* usys = reinterpret_cast<int*>(base + L.off_usys);
-  rc = launch_units(offsets, nsys, ntotal, ustart, usys, st);
+  rc = launch_units(offsets, nsys, ntotal, L.plan.unit, ustart, usys, st);
   if (rc) return rc;
-  return launch_scf_force_batched(x, y, z, offsets, ustart, usys, nsys, ntotal, nmax, lmax, A, B,
-                                  precision, outputs, pot, ax, ay, az, base + L.off_prep, st);
+  return launch_scf_force_batched(L.plan, x, y, z, offsets, ustart, usys, nsys, ntotal, A, B, outputs,
+                                  pot, ax, ay, az, base + L.off_prep, st);
+}
+
+size_t etics_hermite_workspace_size(int64_t ntotal, int nsys, int nmax, int lmax, int precision) {
+  if (ntotal < 0 || nsys < 1 || !valid_cut(nmax, lmax) || !valid_prec(precision)) return 0;
+  if (ntotal / kMinUnitParticles + nsys > INT32_MAX / 2) return 0;
+  return hermite_ws_bytes(ntotal, nsys, nmax, lmax, precision);
+}
+
+int etics_hermite_scf_batched(double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                              const double* m, const int64_t* offsets, int nsys, int64_t ntotal,
+                              int nmax, int lmax, int precision, double dt, int nsteps, int flags,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  int rc = check_batched(ntotal, nsys, nmax, lmax, precision, offsets);
+  if (rc) return rc;
+  if (nsteps < 0) return einval("nsteps < 0");
+  if (!(dt == dt)) return einval("dt is NaN");
+  if (ntotal > 0 && (!x || !y || !z || !vx || !vy || !vz || !m)) return einval("state pointer is NULL");
+  rc = check_ws(workspace, ws_bytes, hermite_ws_bytes(ntotal, nsys, nmax, lmax, precision));
+  if (rc) return rc;
+  if (nsteps == 0 || ntotal == 0) return ETICS_OK;
+  return run_hermite(x, y, z, vx, vy, vz, m, offsets, nsys, ntotal, nmax, lmax, precision, dt, nsteps, flags,
+                     workspace, ws_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
 int etics_leapfrog_scf_batched(double* x, double* y, double* z, double* vx, double* vy, double* vz,
@@ -307,6 +442,10 @@ int etics_leapfrog_scf_batched(double* x, double* y, double* z, double* vx, doub
   if (!(dt == dt)) return einval("dt is NaN");
   if (ntotal > 0 && (!x || !y || !z || !vx || !vy || !vz || !m)) return einval("state pointer is NULL");
   const BatchedLayout L = batched_layout(ntotal, nsys, nmax, lmax, precision);
+  if (!L.ok) {
+    set_error("no tile plan for these cutoffs");
+    return ETICS_EUNSUPPORTED;
+  }
   if (!workspace || ws_bytes < L.total) {
     set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
     return ETICS_EWORKSPACE;

@@ -1,12 +1,13 @@
 // etics_batched.hip -- many independent systems in one launch, and the leapfrog.
 //
 // Systems are stored back to back (offsets[nsys+1], on the device).  The work is cut
-// into units of at most kUnitParticles particles of one system: batched_units_kernel
+// into units of at most `unit` particles of one system (the plan's; 4096 unless the
+// tuner chose another): batched_units_kernel
 // builds, on the device, the first unit of every system (ustart) and the system of
 // every unit (usys).  The batched coefficient kernel gives each unit its own partial
 // slot and the batched reduction sums a system's slots in unit order, so every
-// system's coefficients are reproducible; the batched force kernel runs one
-// workgroup per unit, so each workgroup reads one system's coefficients.
+// system's coefficients are reproducible; the batched force kernel runs a few
+// workgroups per unit, so each workgroup reads one system's coefficients.
 //
 // Leapfrog (the paper integrates with a leapfrog, Section 3.4), kick-drift-kick:
 //   v += dt/2 a(x);  x += dt v;  a = a(x);  v += dt/2 a.
@@ -22,6 +23,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <string>
 
 #include "etics_internal.hpp"
 
@@ -32,14 +34,14 @@ __device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
 
-__device__ __forceinline__ int system_units(const int64_t* off, int s, int64_t ntotal) {
+__device__ __forceinline__ int system_units(const int64_t* off, int s, int64_t ntotal, int unit) {
   const int64_t b = clamp64(off[s], 0, ntotal);
   const int64_t e = clamp64(off[s + 1], b, ntotal);
-  return int((e - b + kUnitParticles - 1) / kUnitParticles);
+  return int((e - b + unit - 1) / unit);
 }
 
 __global__ __launch_bounds__(1024) void batched_units_kernel(const int64_t* __restrict__ offsets,
-                                                             int nsys, int64_t ntotal,
+                                                             int nsys, int64_t ntotal, int unit,
                                                              int* __restrict__ ustart,
                                                              int* __restrict__ usys) {
   __shared__ int part[1024];
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(1024) void batched_units_kernel(const int64_t* __re
   const int a = t * per < nsys ? t * per : nsys;
   const int b = a + per < nsys ? a + per : nsys;
   int cnt = 0;
-  for (int s = a; s < b; ++s) cnt += system_units(offsets, s, ntotal);
+  for (int s = a; s < b; ++s) cnt += system_units(offsets, s, ntotal, unit);
   part[t] = cnt;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(1024) void batched_units_kernel(const int64_t* __re
   int run = t > 0 ? part[t - 1] : 0;
   for (int s = a; s < b; ++s) {
     ustart[s] = run;
-    const int nu = system_units(offsets, s, ntotal);
+    const int nu = system_units(offsets, s, ntotal, unit);
     for (int j = 0; j < nu; ++j) usys[run + j] = s;
     run += nu;
   }
@@ -95,8 +97,10 @@ __global__ __launch_bounds__(256) void lf_kick_drift_kernel(double* __restrict__
 // ------------------------------------------------------------------ host side
 BatchedLayout batched_layout(int64_t ntotal, int nsys, int nmax, int lmax, int prec) {
   BatchedLayout L{};
+  L.ok = make_coeff_plan(ntotal, nmax, lmax, prec, &L.plan, kBasisHO, true);
+  if (!L.ok) return L;
   const int K = coeff_count(nmax, lmax);
-  const int mu = max_units(ntotal, nsys);
+  const int mu = max_units(ntotal, nsys, L.plan.unit);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -116,9 +120,9 @@ BatchedLayout batched_layout(int64_t ntotal, int nsys, int nmax, int lmax, int p
   return L;
 }
 
-int launch_units(const int64_t* offsets, int nsys, int64_t ntotal, int* ustart, int* usys,
+int launch_units(const int64_t* offsets, int nsys, int64_t ntotal, int unit, int* ustart, int* usys,
                  hipStream_t st) {
-  hipLaunchKernelGGL(batched_units_kernel, dim3(1), dim3(1024), 0, st, offsets, nsys, ntotal,
+  hipLaunchKernelGGL(batched_units_kernel, dim3(1), dim3(1024), 0, st, offsets, nsys, ntotal, unit,
                      ustart, usys);
   return hip_fail(hipGetLastError(), "batched_units_kernel launch");
 }
@@ -136,13 +140,15 @@ struct LeapfrogCall {
   void* ws;
   size_t ws_bytes;
   int device;
+  int plan[6];  // tile shape of the plan the step was captured with
 };
 
 bool same_call(const LeapfrogCall& a, const LeapfrogCall& b) {
   return a.x == b.x && a.y == b.y && a.z == b.z && a.vx == b.vx && a.vy == b.vy && a.vz == b.vz &&
          a.m == b.m && a.offsets == b.offsets && a.nsys == b.nsys && a.ntotal == b.ntotal &&
          a.nmax == b.nmax && a.lmax == b.lmax && a.prec == b.prec && a.dt == b.dt &&
-         a.ws == b.ws && a.ws_bytes == b.ws_bytes && a.device == b.device;
+         a.ws == b.ws && a.ws_bytes == b.ws_bytes && a.device == b.device &&
+         std::memcmp(a.plan, b.plan, sizeof a.plan) == 0;
 }
 
 struct Parts {
@@ -153,8 +159,7 @@ struct Parts {
   double *A, *B, *ax, *ay, *az;
 };
 
-Parts parts_of(const LeapfrogCall& c) {
-  const BatchedLayout L = batched_layout(c.ntotal, c.nsys, c.nmax, c.lmax, c.prec);
+Parts parts_of(const LeapfrogCall& c, const BatchedLayout& L) {
   char* base = reinterpret_cast<char*>(c.ws);
   Parts p;
   p.ustart = reinterpret_cast<int*>(base + L.off_ustart);
@@ -174,9 +179,8 @@ int accelerations(const LeapfrogCall& c, const CoeffPlan& plan, const Parts& p, 
   int rc = launch_scf_coeffs_batched(plan, c.x, c.y, c.z, c.m, c.offsets, p.ustart, p.usys, c.nsys,
                                      c.ntotal, p.A, p.B, p.partials, st);
   if (rc) return rc;
-  return launch_scf_force_batched(c.x, c.y, c.z, c.offsets, p.ustart, p.usys, c.nsys, c.ntotal,
-                                  c.nmax, c.lmax, p.A, p.B, c.prec, ETICS_ACC, nullptr, p.ax, p.ay,
-                                  p.az, p.prep, st);
+  return launch_scf_force_batched(plan, c.x, c.y, c.z, c.offsets, p.ustart, p.usys, c.nsys, c.ntotal,
+                                  p.A, p.B, ETICS_ACC, nullptr, p.ax, p.ay, p.az, p.prep, st);
 }
 
 // the opening kick and drift of the first step, from the accelerations in p.ax..p.az
@@ -198,9 +202,9 @@ int step_tail(const LeapfrogCall& c, const CoeffPlan& plan, const Parts& p, bool
                                      c.ntotal, p.A, p.B, p.partials, st);
   if (rc) return rc;
   LfUpdate lf{c.x, c.y, c.z, c.vx, c.vy, c.vz, 0.5 * c.dt, c.dt, last ? 1 : 2};
-  return launch_scf_force_batched(c.x, c.y, c.z, c.offsets, p.ustart, p.usys, c.nsys, c.ntotal,
-                                  c.nmax, c.lmax, p.A, p.B, c.prec, ETICS_ACC, nullptr, p.ax, p.ay,
-                                  p.az, p.prep, st, &lf);
+  return launch_scf_force_batched(plan, c.x, c.y, c.z, c.offsets, p.ustart, p.usys, c.nsys,
+                                  c.ntotal, p.A, p.B, ETICS_ACC, nullptr, p.ax, p.ay, p.az, p.prep,
+                                  st, &lf);
 }
 
 struct GraphCache {
@@ -228,7 +232,7 @@ int run_leapfrog(double* x, double* y, double* z, double* vx, double* vy, double
                  const double* m, const int64_t* offsets, int nsys, int64_t ntotal, int nmax,
                  int lmax, int prec, double dt, int nsteps, int flags, void* ws, size_t ws_bytes,
                  hipStream_t st) {
-  LeapfrogCall c{x, y, z, vx, vy, vz, m, offsets, nsys, ntotal, nmax, lmax, prec, dt, ws, ws_bytes, 0};
+  LeapfrogCall c{x, y, z, vx, vy, vz, m, offsets, nsys, ntotal, nmax, lmax, prec, dt, ws, ws_bytes, 0, {}};
   // timing events are not recorded inside the steps (they would be captured too)
   struct HookPause {
     bool prev;
@@ -237,13 +241,20 @@ int run_leapfrog(double* x, double* y, double* z, double* vx, double* vy, double
   } pause;
   int rc = hip_fail(hipGetDevice(&c.device), "hipGetDevice");
   if (rc) return rc;
-  CoeffPlan plan;
-  if (!make_coeff_plan(kUnitParticles, nmax, lmax, prec, &plan)) {
+  const BatchedLayout L = batched_layout(ntotal, nsys, nmax, lmax, prec);
+  if (!L.ok) {
     set_error("no tile plan for these cutoffs");
     return ETICS_EUNSUPPORTED;
   }
-  const Parts p = parts_of(c);
-  rc = launch_units(offsets, nsys, ntotal, p.ustart, p.usys, st);
+  if (ws_bytes < L.total) {
+    set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
+    return ETICS_EWORKSPACE;
+  }
+  const CoeffPlan& plan = L.plan;
+  const int shape[6] = {plan.nw, plan.tp, plan.streams, plan.grid_mult, plan.unit, plan.split};
+  std::memcpy(c.plan, shape, sizeof shape);
+  const Parts p = parts_of(c, L);
+  rc = launch_units(offsets, nsys, ntotal, plan.unit, p.ustart, p.usys, st);
   if (rc) return rc;
   if (nsteps < 1) return ETICS_OK;
   rc = accelerations(c, plan, p, st);  // a(x) at the start of the first step

@@ -1,29 +1,10 @@
-// etics_coeff.hip -- SCF expansion coefficients on gfx950 (MI355X).
+// etics_coeff.hip -- SCF expansion coefficients on gfx950 (MI355X): host side.
 //
-// The first part of an SCF force calculation (paper Section 3.3) is the sum over all
-// particles k of m_k PhiT_nl(r_k) Ybar_lm(theta_k) (cos, sin)(m phi_k) for every
-// (n, l, m) (eq. scf-phi with the Hernquist-Ostriker basis of Section 2.5).
-//
-// scf_coeff_kernel: each workgroup (4 wavefronts) walks a contiguous run of tiles of
-//   `tp` particles.
-//   Phase 1 evaluates each particle's basis once, one particle per lane.  The basis
-//   is split into independent jobs -- the Gegenbauer row of one l (radial job) and
-//   the Legendre column of one m times (cos, sin)(m phi) and the radial prefactor
-//   (angular job) -- and a compile-time plan gives each job to one wavefront of a
-//   particle group: the four wavefronts share the work of the same 64 particles, or
-//   (small cutoffs, NW = 2 or 1) form 2 or 4 groups of 64 particles.  The values go to
-//   LDS at compile-time offsets.
-//   Phase 2 is an outer-product accumulation over the tile: every lane owns an
-//   nb x bs register block of coefficients (radial orders x angular slots of one l)
-//   and accumulates the products of the LDS-staged radial and angular values.  The
-//   lanes are grouped in "streams": each stream owns one copy of every block and
-//   takes every streams-th particle of the tile.  FP32 partial sums are folded into
-//   FP64 (or compensated double-float) accumulators every few tiles.
-//   At the end the streams are merged in a fixed order through LDS and the
-//   workgroup writes one partial coefficient vector.
-// scf_reduce_kernel sums the partial vectors over workgroups in a fixed order and
-//   applies (2 - delta_m0) Atilde_nl and the basis constants, so the result does not
-//   depend on how the hardware schedules workgroups.
+// The coefficient kernels themselves are in etics_coeff_wg.hpp.  This file holds the
+// fixed-order reductions that sum the per-workgroup (or per-unit) partial vectors and
+// apply (2 - delta_m0) Atilde_nl and the basis constants, the tile plans (fixed rules
+// and tuned overrides), and the launches of the coefficient sums of one system, of
+// batched systems and of the allocation-free entry point.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -31,547 +12,11 @@
 #include <cstdint>
 #include <mutex>
 
+#include "etics_coeff_wg.hpp"
 #include "etics_device.hpp"
 #include "etics_internal.hpp"
 
 namespace etics {
-
-struct CoeffArgs {
-  const double *x, *y, *z, *m;
-  int64_t n;
-  void* partials;  // [grid][2K] FP64 (or double-float pairs)
-  int K, nmax, lmax, tp, nblocks, streams, flush_tiles, ntiles, nchunks;
-};
-
-// ------------------------------------------------------------ phase-1 job plan
-// The basis jobs of a cutoff bucket are split between the NW wavefronts that share a
-// group of 64 particles (NW = 4: the whole workgroup; NW = 2 or 1: two or four groups,
-// so a tile holds 128 or 256 particles).  Angular job m (the Legendre column of m times
-// (cos, sin)(m phi)) costs ~6 operations per l in [m, lb]; before it, a wavefront walks
-// the diagonal from m = 0 up to the largest column it owns (~6 operations per step), so
-// each wavefront gets a contiguous range of columns and the low columns go together.
-// Radial job l (a Gegenbauer row) costs ~2 operations per padded order; a wavefront
-// with radial jobs only needs xi alone, not the angles.  The plan is the contiguous
-// split (searched over all cut points) with the smallest max + total/4 load, radial
-// jobs added greedily to the least loaded wavefront.
-template <int LB, int NRP, int NW>
-struct JobPlan {
-  int ownerZ[LB + 1];
-  int ownerG[LB + 1];
-  int maxm[NW];
-};
-
-template <int LB, int NRP, int NW>
-constexpr JobPlan<LB, NRP, NW> make_job_plan() {
-  constexpr int kDiag = 6, kSphSave = 25;
-  constexpr int kRad = 2 * NRP + NRP / 4 + 2;
-  auto zcost = [](int m) { return 6 * (LB - m + 1) + 8; };
-  JobPlan<LB, NRP, NW> best{};
-  long best_key = -1;
-  // k = number of wavefronts with angular columns; cut[i] = first column of range i+1
-  for (int k = 1; k <= NW && k <= LB + 1; ++k) {
-    int cut[NW + 1] = {};
-    for (int i = 0; i < k - 1; ++i) cut[i] = i + 1;  // first combination of k-1 cuts
-    while (true) {
-      JobPlan<LB, NRP, NW> p{};
-      int load[NW] = {};
-      for (int w = 0; w < NW; ++w) p.maxm[w] = -1;
-      int lo = 0;
-      for (int r = 0; r < k; ++r) {
-        const int hi = (r < k - 1 ? cut[r] : LB + 1) - 1;
-        for (int m = lo; m <= hi; ++m) {
-          p.ownerZ[m] = r;
-          load[r] += zcost(m);
-        }
-        load[r] += kDiag * hi;
-        p.maxm[r] = hi;
-        lo = hi + 1;
-      }
-      for (int w = k; w < NW; ++w) load[w] = -kSphSave;
-      for (int l = 0; l <= LB; ++l) {
-        int w = 0;
-        for (int q = 1; q < NW; ++q)
-          if (load[q] < load[w]) w = q;
-        p.ownerG[l] = w;
-        load[w] += kRad;
-      }
-      long mx = load[0], tot = 0;
-      for (int w = 0; w < NW; ++w) {
-        tot += load[w];
-        if (load[w] > mx) mx = load[w];
-      }
-      const long key = 4 * mx + tot;
-      if (best_key < 0 || key < best_key) {
-        best_key = key;
-        best = p;
-      }
-      // next combination of k-1 cut points from 1..LB (increasing)
-      int i = k - 2;
-      while (i >= 0 && cut[i] == LB - (k - 2 - i)) --i;
-      if (i < 0) break;
-      ++cut[i];
-      for (int j = i + 1; j < k - 1; ++j) cut[j] = cut[j - 1] + 1;
-    }
-  }
-  return best;
-}
-
-// wide accumulator: MODE 0 -> FP64; MODE 1 -> compensated FP32 pair (hi, lo)
-template <typename T, int MODE>
-struct Wide;
-template <>
-struct Wide<float, 0> {
-  double v = 0.0;
-  __device__ void add(float a) { v += double(a); }
-};
-template <>
-struct Wide<float, 1> {
-  float hi = 0.f, lo = 0.f;
-  __device__ void add(float a) {  // Knuth TwoSum, error carried in lo
-    float s = hi + a;
-    float bb = s - hi;
-    float err = (hi - (s - bb)) + (a - bb);
-    hi = s;
-    lo += err;
-  }
-};
-template <>
-struct Wide<double, 0> {
-  double v = 0.0;
-  __device__ void add(double a) { v += a; }
-};
-
-template <int MODE>
-struct PartialT;
-template <>
-struct PartialT<0> {
-  using type = double;
-};
-template <>
-struct PartialT<1> {
-  using type = float2;
-};
-
-__device__ __forceinline__ double wide_value(const Wide<float, 0>& w) { return w.v; }
-__device__ __forceinline__ double wide_value(const Wide<double, 0>& w) { return w.v; }
-__device__ __forceinline__ float2 wide_value(const Wide<float, 1>& w) { return make_float2(w.hi, w.lo); }
-
-__device__ __forceinline__ double merge(double a, double b) { return a + b; }
-__device__ __forceinline__ float2 merge(float2 a, float2 b) {  // double-float addition
-  float s = a.x + b.x;
-  float bb = s - a.x;
-  float err = (a.x - (s - bb)) + (b.x - bb);
-  err += a.y + b.y;
-  float hi = s + err;
-  float lo = err - (hi - s);
-  return make_float2(hi, lo);
-}
-
-// two adjacent LDS values in one store (the address is 2-element aligned)
-__device__ __forceinline__ void store_pair(float* p, float a, float b) {
-  *reinterpret_cast<float2*>(p) = make_float2(a, b);
-}
-__device__ __forceinline__ void store_pair(double* p, double a, double b) {
-  *reinterpret_cast<double2*>(p) = make_double2(a, b);
-}
-
-// decode register block b of a cutoff (lmax, nchunks) into (l, n0, s0)
-template <int NB, int BS>
-__device__ __forceinline__ void decode_block(int b, int lmax, int nchunks, int& bl, int& n0,
-                                             int& s0) {
-  bl = 0;
-  n0 = 0;
-  s0 = 0;
-  for (int l = 0; l <= lmax; ++l) {
-    const int nsc = slot_pad(l, BS) / BS;
-    const int cnt = nchunks * nsc;
-    if (b < cnt) {
-      bl = l;
-      n0 = (b / nsc) * NB;
-      s0 = (b % nsc) * BS;
-      return;
-    }
-    b -= cnt;
-  }
-}
-
-// plain vector types for reads through LDS (address space 3) pointers
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(3))) f32x4 LdsF32x4;
-typedef __attribute__((address_space(3))) f64x2 LdsF64x2;
-
-// One workgroup's share of the coefficient sums: the LDS tile, the register block
-// of each lane, and the three steps (basis -> LDS, accumulate, merge and write).
-template <typename T, int LB, int NB, int BS, int MODE, int NW>
-struct CoeffWG {
-  static_assert(NW == 1 || NW == 2 || NW == 4, "wavefronts per particle group");
-  static constexpr int NRP = nrp_for_nb(NB);
-  static constexpr int SPG = g_stride(LB, NRP);
-  static constexpr int SPZ = z_stride(LB, BS);
-  using PT = typename PartialT<(sizeof(T) == 4 && MODE == 1) ? 1 : 0>::type;
-
-  T* G;  // [tp][SPG]  radial values, rows of NRP per l
-  T* Z;  // [tp][SPZ]  angular values x mass x radial prefactor
-  int tid, lane, wave, rank, pidx, maxm_w, lmax, nmax, tp, streams, nblocks, nchunks;
-  int my_stream, my_block, bl, n0, s0;
-  int goff, zoff0;  // this lane's block in a particle's radial / angular row
-  bool active;
-  T acc[NB][BS];
-  Wide<T, MODE> wide[NB][BS];
-
-  __device__ __forceinline__ void init(unsigned char* lds, int tp_, int lmax_, int nmax_,
-                                       int nblocks_, int streams_, int nchunks_) {
-    constexpr JobPlan<LB, NRP, NW> kJP = make_job_plan<LB, NRP, NW>();
-    G = reinterpret_cast<T*>(lds);
-    Z = G + tp_ * SPG;
-    tid = threadIdx.x;
-    lane = tid & 63;
-    wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    rank = wave % NW;               // job share within the particle group
-    pidx = (wave / NW) * 64 + lane;  // this lane's particle in the tile (phase 1)
-    tp = tp_;
-    lmax = lmax_;
-    nmax = nmax_;
-    nblocks = nblocks_;
-    streams = streams_;
-    nchunks = nchunks_;
-    // largest angular column owned by this wavefront (the diagonal walk stops there)
-    maxm_w = -1;
-    static_for<NW>([&](auto wc) {
-      if (rank == decltype(wc)::value) maxm_w = kJP.maxm[decltype(wc)::value];
-    });
-    my_stream = tid / nblocks;
-    my_block = tid - my_stream * nblocks;
-    active = my_stream < streams;
-    decode_block<NB, BS>(my_block, lmax, nchunks, bl, n0, s0);
-    goff = bl * NRP + n0;
-    zoff0 = zoff_rt<BS>(bl) + s0;
-    clear_acc();
-    clear_wide();
-  }
-
-  __device__ __forceinline__ void clear_acc() {
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int j = 0; j < BS; ++j) acc[i][j] = T(0);
-  }
-  __device__ __forceinline__ void clear_wide() {
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int j = 0; j < BS; ++j) wide[i][j] = Wide<T, MODE>{};
-  }
-  // angular padding slots are never written by phase 1; keep them finite
-  __device__ __forceinline__ void zero_slots() {
-    for (int i = tid; i < tp * SPZ; i += kCoeffThreads) Z[i] = T(0);
-  }
-  // fold the FP32 run into the wide accumulators
-  __device__ __forceinline__ void fold() {
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int j = 0; j < BS; ++j) {
-        wide[i][j].add(acc[i][j]);
-        acc[i][j] = T(0);
-      }
-  }
-
-  // phase 1: basis of the particle of this lane (zero mass for an empty lane)
-  __device__ __forceinline__ void phase1(double xd, double yd, double zd, double md) {
-    if (pidx >= tp) return;
-    T* Gp = G + pidx * SPG;
-    T* Zp = Z + pidx * SPZ;
-    T xi;
-    if (maxm_w >= 0) {
-      const Sph<T> s = sph<T>(xd, yd, zd);
-      xi = s.xi;
-      angular_jobs(s, md, Zp);
-    } else {  // radial jobs only: xi = (r - 1) / (r + 1) alone
-      const T x = T(xd), y = T(yd), z = T(zd);
-      const T r = sqrt_(x * x + y * y + z * z);
-      const T u = rcp_(T(1) + r);
-      xi = r * u - u;
-    }
-    radial_jobs(xi, Gp);
-  }
-
-  // angular jobs: column m of mass u (tu)^l Ybar_lm (cos, sin)(m phi), l = m..lmax.  The
-  // diagonal value mass u (tu)^m Ybar_mm and (cos, sin)(m phi) are walked up to the
-  // largest column this wavefront owns.
-  __device__ __forceinline__ void angular_jobs(const Sph<T>& s, double md, T* Zp) {
-    constexpr JobPlan<LB, NRP, NW> kJP = make_job_plan<LB, NRP, NW>();
-    const T tu = s.t * s.u, ctu = s.ct * tu, tu2 = tu * tu, stu = s.st * tu;
-    T Pd = T(md) * s.u * T(kTab.c1[0][0]);
-    T cmc = T(1), smc = T(0);
-    static_for<LB + 1>([&](auto mc) {
-      constexpr int m = decltype(mc)::value;
-      if constexpr (m > 0) {
-        if (m <= maxm_w) {
-          Pd = (T(kTab.c1[m][m]) * stu) * Pd;
-          const T c2 = cmc * s.cp - smc * s.sp;
-          smc = smc * s.cp + cmc * s.sp;
-          cmc = c2;
-        }
-      }
-      if (rank == kJP.ownerZ[m] && m <= lmax) {
-        T P2 = T(0), P1 = Pd;  // P2 is first read at l = m + 2
-        auto put = [&](auto lc2, T P) {
-          constexpr int l = decltype(lc2)::value;
-          if constexpr (m == 0) {
-            Zp[zoff(l, BS) + 2 * l] = P;
-          } else {  // (cos, sin) pair at an even slot of an 8-byte aligned row
-            store_pair(Zp + zoff(l, BS) + 2 * m - 2, P * cmc, P * smc);
-          }
-        };
-        // the whole column up to the bucket's LB (rows past lmax are never read), so
-        // the recurrence runs without a branch per row
-        put(std::integral_constant<int, m>{}, P1);
-        static_for<LB - m>([&](auto kc) {
-          constexpr int l = m + 1 + decltype(kc)::value;
-          T P = (T(kTab.c1[l][m]) * ctu) * P1;
-          if constexpr (l > m + 1) P -= (T(kTab.c2[l][m]) * tu2) * P2;
-          P2 = P1;
-          P1 = P;
-          put(std::integral_constant<int, l>{}, P);
-        });
-      }
-    });
-  }
-
-  // radial jobs: monic Gegenbauer Chat_n^(2l+3/2)(xi), n = 0..NRP-1.  Entries past nmax
-  // only feed coefficients that are never written out; they stay finite.
-  __device__ __forceinline__ void radial_jobs(T xi, T* Gp) {
-    constexpr JobPlan<LB, NRP, NW> kJP = make_job_plan<LB, NRP, NW>();
-    static_for<LB + 1>([&](auto lc) {
-      constexpr int l = decltype(lc)::value;
-      if (rank == kJP.ownerG[l] && l <= lmax) {
-        T p2 = T(1), p1 = T(0);
-        static_for<NRP / 4>([&](auto qc) {
-          constexpr int nb4 = 4 * decltype(qc)::value;
-          T v[4];
-          static_for<4>([&](auto jc) {
-            constexpr int nn = nb4 + decltype(jc)::value;
-            const T c = xi * p1 - T(kTab.q[l][nn]) * p2;
-            p2 = p1;
-            p1 = c;
-            v[decltype(jc)::value] = c;
-          });
-          T* row = Gp + l * NRP + nb4;
-          if constexpr (sizeof(T) == 4) {
-            *reinterpret_cast<float4*>(row) = make_float4(v[0], v[1], v[2], v[3]);
-          } else {
-            *reinterpret_cast<double2*>(row) = make_double2(v[0], v[1]);
-            *reinterpret_cast<double2*>(row + 2) = make_double2(v[2], v[3]);
-          }
-        });
-      }
-    });
-  }
-
-  // phase 2: outer-product accumulation over the tile.  LDS positions are 32-bit
-  // element offsets from the tile base.
-  __device__ __forceinline__ void phase2() {
-    if (!active) return;
-    using LT = __attribute__((address_space(3))) const T;
-    LT* gs = (LT*)(G);
-    LT* zs = (LT*)(Z);
-    constexpr int NG = (NB + 3) / 4 * 4;
-    T gv[2][NG], zv[2][BS];
-    auto fetch = [&](int go, int zo, int buf) {
-      LT* g = gs + go;
-      LT* zz = zs + zo;
-      if constexpr (sizeof(T) == 4) {
-#pragma unroll
-        for (int q = 0; q < NG / 4; ++q) {
-          const f32x4 f = reinterpret_cast<const LdsF32x4*>(g)[q];
-          gv[buf][4 * q] = f.x;
-          gv[buf][4 * q + 1] = f.y;
-          gv[buf][4 * q + 2] = f.z;
-          gv[buf][4 * q + 3] = f.w;
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < (NB + 1) / 2; ++q) {
-          const f64x2 f = reinterpret_cast<const LdsF64x2*>(g)[q];
-          gv[buf][2 * q] = f.x;
-          gv[buf][2 * q + 1] = f.y;
-        }
-      }
-      static_assert(BS % 4 == 0, "angular blocks are read in aligned 4-slot groups");
-#pragma unroll
-      for (int j = 0; j < BS; j += 4) {
-        if constexpr (sizeof(T) == 4) {
-          const f32x4 f = reinterpret_cast<const LdsF32x4*>(zz)[j / 4];
-          zv[buf][j] = f.x;
-          zv[buf][j + 1] = f.y;
-          zv[buf][j + 2] = f.z;
-          zv[buf][j + 3] = f.w;
-        } else {
-          const f64x2 f0 = reinterpret_cast<const LdsF64x2*>(zz)[j / 2];
-          const f64x2 f1 = reinterpret_cast<const LdsF64x2*>(zz)[j / 2 + 1];
-          zv[buf][j] = f0.x;
-          zv[buf][j + 1] = f0.y;
-          zv[buf][j + 2] = f1.x;
-          zv[buf][j + 3] = f1.y;
-        }
-      }
-    };
-    auto madd = [&](int buf) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int j = 0; j < BS; ++j) acc[i][j] = fma_(gv[buf][i], zv[buf][j], acc[i][j]);
-    };
-    // two particles per trip, each one's LDS reads issued before the other's FMAs.  The
-    // look-ahead read past the tile is clamped to its last particle (read, never used),
-    // so the reads need no branch and the two buffers keep their registers.
-    const int gstep = streams * SPG, zstep = streams * SPZ;
-    const int glast = goff + (tp - 1) * SPG, zlast = zoff0 + (tp - 1) * SPZ;
-    int p = my_stream;
-    int go = goff + p * SPG, zo = zoff0 + p * SPZ;
-    fetch(go < glast ? go : glast, zo < zlast ? zo : zlast, 0);
-    for (; p + streams < tp; p += 2 * streams) {
-      fetch(go + gstep, zo + zstep, 1);
-      madd(0);
-      go += 2 * gstep;
-      zo += 2 * zstep;
-      fetch(go < glast ? go : glast, zo < zlast ? zo : zlast, 0);
-      madd(1);
-    }
-    if (p < tp) madd(0);
-  }
-
-  // merge the streams in a fixed order through LDS (overwrites the tile) and write the
-  // partial sums in coefficient layout: part[0..K) cos, part[K..2K) sin
-  __device__ __forceinline__ void merge_write(unsigned char* lds, PT* part, int K) {
-    PT* out = reinterpret_cast<PT*>(lds);
-    for (int s = 0; s < streams; ++s) {
-      if (active && my_stream == s) {
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int j = 0; j < BS; ++j) {
-            const int e = (my_block * NB + i) * BS + j;
-            const PT v = wide_value(wide[i][j]);
-            out[e] = (s == 0) ? v : merge(out[e], v);
-          }
-      }
-      __syncthreads();
-    }
-    const int L2 = (lmax + 1) * (lmax + 2) / 2;
-    const int nent = nblocks * NB * BS;
-    for (int e = tid; e < nent; e += kCoeffThreads) {
-      const int j = e % BS;
-      const int i = (e / BS) % NB;
-      int l, nb0, sb0;
-      decode_block<NB, BS>(e / (NB * BS), lmax, nchunks, l, nb0, sb0);
-      const int nn = nb0 + i;
-      const int slot = sb0 + j;
-      if (nn > nmax || slot > 2 * l) continue;
-      const int m = slot == 2 * l ? 0 : slot / 2 + 1;
-      const bool is_sin = slot < 2 * l && (slot & 1) == 1;
-      const int k = nn * L2 + l * (l + 1) / 2 + m;
-      part[(is_sin ? K : 0) + k] = out[e];
-    }
-  }
-};
-
-template <typename T, int LB, int NB, int BS, int MODE, int NW>
-__global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coeff_kernel(
-    const CoeffArgs a) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  CoeffWG<T, LB, NB, BS, MODE, NW> w;
-  w.init(lds_raw, a.tp, a.lmax, a.nmax, a.nblocks, a.streams, a.nchunks);
-  w.zero_slots();
-  __syncthreads();
-
-  // each workgroup takes a contiguous run of tiles, so the cache lines shared by two
-  // neighbouring tiles are fetched once, into one L2
-  const int t0 = int(int64_t(blockIdx.x) * a.ntiles / gridDim.x);
-  const int t1 = int(int64_t(blockIdx.x + 1) * a.ntiles / gridDim.x);
-  // particle data of the first tile (later tiles are prefetched during phase 2)
-  double xd = 0.0, yd = 0.0, zd = 0.0, md = 0.0;
-  auto load_particle = [&](int tile) {
-    const int64_t pi = int64_t(tile) * a.tp + w.pidx;
-    const bool valid = tile < t1 && w.pidx < a.tp && pi < a.n;
-    xd = valid ? a.x[pi] : 0.0;
-    yd = valid ? a.y[pi] : 0.0;
-    zd = valid ? a.z[pi] : 0.0;
-    md = valid ? a.m[pi] : 0.0;
-  };
-  load_particle(t0);
-
-  int tcount = 0;
-  for (int tile = t0; tile < t1; ++tile) {
-    w.phase1(xd, yd, zd, md);
-    __syncthreads();
-    load_particle(tile + 1);  // next tile's particles load while phase 2 runs
-    w.phase2();
-    if (++tcount == a.flush_tiles) {
-      tcount = 0;
-      w.fold();
-    }
-    __syncthreads();
-  }
-  w.fold();
-  using PT = typename CoeffWG<T, LB, NB, BS, MODE, NW>::PT;
-  w.merge_write(lds_raw, reinterpret_cast<PT*>(a.partials) + size_t(blockIdx.x) * 2 * a.K, a.K);
-}
-
-// Batched systems: the work is cut into units of at most kUnitParticles particles of
-// one system (unit u of system s covers its particles from (u - ustart[s]) *
-// kUnitParticles on); each unit's sums go to their own partial slot, so the per-system
-// reduction below has a fixed order whatever the schedule.
-struct BatchedCoeffArgs {
-  const double *x, *y, *z, *m;
-  const int64_t* offsets;
-  const int* ustart;  // [nsys+1] first unit of each system; ustart[nsys] = number of units
-  const int* usys;    // [units] system of each unit
-  int64_t ntotal;
-  void* partials;     // [units][2K]
-  int nsys, K, nmax, lmax, tp, nblocks, streams, nchunks, flush_tiles;
-};
-
-template <typename T, int LB, int NB, int BS, int MODE, int NW>
-__global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coeff_batched_kernel(
-    const BatchedCoeffArgs a) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  using W = CoeffWG<T, LB, NB, BS, MODE, NW>;
-  W w;
-  w.init(lds_raw, a.tp, a.lmax, a.nmax, a.nblocks, a.streams, a.nchunks);
-  const int nunits = a.ustart[a.nsys];
-  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
-    const int s = a.usys[u];
-    int64_t b = a.offsets[s], e = a.offsets[s + 1];
-    b = b < 0 ? 0 : (b > a.ntotal ? a.ntotal : b);
-    e = e < b ? b : (e > a.ntotal ? a.ntotal : e);
-    const int64_t ub = b + int64_t(u - a.ustart[s]) * kUnitParticles;
-    const int64_t ue = ub + kUnitParticles < e ? ub + kUnitParticles : e;
-    const int ntiles = int((ue - ub + a.tp - 1) / a.tp);
-    w.zero_slots();
-    w.clear_wide();
-    __syncthreads();
-    int tcount = 0;
-    for (int tile = 0; tile < ntiles; ++tile) {
-      const int64_t pi = ub + int64_t(tile) * a.tp + w.pidx;
-      const bool valid = w.pidx < a.tp && pi < ue;
-      w.phase1(valid ? a.x[pi] : 0.0, valid ? a.y[pi] : 0.0, valid ? a.z[pi] : 0.0,
-               valid ? a.m[pi] : 0.0);
-      __syncthreads();
-      w.phase2();
-      if (++tcount == a.flush_tiles) {
-        tcount = 0;
-        w.fold();
-      }
-      __syncthreads();
-    }
-    w.fold();
-    w.merge_write(lds_raw, reinterpret_cast<typename W::PT*>(a.partials) + size_t(u) * 2 * a.K, a.K);
-    __syncthreads();
-  }
-}
 
 // ------------------------------------------------------------ fixed-order reduce
 struct ReduceArgs {
@@ -654,103 +99,82 @@ int launch_fill_zero(double* p, int64_t count, hipStream_t st) {
   return hip_fail(hipGetLastError(), "fill_zero_kernel launch");
 }
 
-// Hernquist-Ostriker normalisation Atilde_nl = 1/I_nl in FP64 (lgamma on the host):
+// Normalisation Atilde_nl = 1/I_nl, I_nl = integral of rhoT_nl PhiT_nl r^2 dr, in FP64
+// (lgamma on the host).
+// Hernquist-Ostriker:
 //   I_nl = -(4 pi K_nl / 2^(8l+6)) Gamma(n+4l+3) / (n! (n+2l+3/2) Gamma(2l+3/2)^2),
 //   K_nl = n(n+4l+3)/2 + (l+1)(2l+1).
-double anl_tilde(int n, int l) {
-  const double Knl = 0.5 * n * (n + 4.0 * l + 3.0) + (l + 1.0) * (2.0 * l + 1.0);
-  const double logI = std::log(4.0 * kPi * Knl) - (8.0 * l + 6.0) * std::log(2.0) +
-                      std::lgamma(n + 4.0 * l + 3.0) - std::lgamma(n + 1.0) -
-                      std::log(n + 2.0 * l + 1.5) - 2.0 * std::lgamma(2.0 * l + 1.5);
+// Clutton-Brock:
+//   I_nl = -pi K_nl 2^(-4l-4) Gamma(n+2l+2) / (n! (n+l+1) (l!)^2),
+//   K_nl = 4n(n+2l+2) + (2l+1)(2l+3).
+double anl_tilde(int n, int l, int basis) {
+  double logI;
+  if (basis == kBasisCB) {
+    const double Knl = 4.0 * n * (n + 2.0 * l + 2.0) + (2.0 * l + 1.0) * (2.0 * l + 3.0);
+    logI = std::log(kPi * Knl) - (4.0 * l + 4.0) * std::log(2.0) + std::lgamma(n + 2.0 * l + 2.0) -
+           std::lgamma(n + 1.0) - std::log(n + l + 1.0) - 2.0 * std::lgamma(l + 1.0);
+  } else {
+    const double Knl = 0.5 * n * (n + 4.0 * l + 3.0) + (l + 1.0) * (2.0 * l + 1.0);
+    logI = std::log(4.0 * kPi * Knl) - (8.0 * l + 6.0) * std::log(2.0) + std::lgamma(n + 4.0 * l + 3.0) -
+           std::lgamma(n + 1.0) - std::log(n + 2.0 * l + 1.5) - 2.0 * std::lgamma(2.0 * l + 1.5);
+  }
   return -std::exp(-logI);
 }
 
 namespace {
-
-template <bool BATCHED, typename T, int LB, int NB, int BS, int MODE, int NW, typename Args>
-int launch_coeff_t(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
-  const void* kfn;
-  if constexpr (BATCHED)
-    kfn = reinterpret_cast<const void*>(scf_coeff_batched_kernel<T, LB, NB, BS, MODE, NW>);
-  else
-    kfn = reinterpret_cast<const void*>(scf_coeff_kernel<T, LB, NB, BS, MODE, NW>);
-  // the kernel has no static LDS: the whole 160 KiB of a CU may be requested (once per
-  // device and kernel)
-  static std::atomic<uint64_t> attr_done{0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-  const uint64_t bit = dev < 64 ? (uint64_t(1) << dev) : 0;
-  if (!bit || !(attr_done.load(std::memory_order_acquire) & bit)) {
-    hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(scf_coeff)");
-    attr_done.fetch_or(bit, std::memory_order_acq_rel);
-  }
-  int rc = hook_before(st);
-  if (rc) return rc;
-  if constexpr (BATCHED)
-    hipLaunchKernelGGL((scf_coeff_batched_kernel<T, LB, NB, BS, MODE, NW>), dim3(grid),
-                       dim3(kCoeffThreads), p.lds_bytes, st, a);
-  else
-    hipLaunchKernelGGL((scf_coeff_kernel<T, LB, NB, BS, MODE, NW>), dim3(grid), dim3(kCoeffThreads),
-                       p.lds_bytes, st, a);
-  rc = hip_fail(hipGetLastError(), "scf_coeff_kernel launch");
-  return rc ? rc : hook_after(st);
-}
-
-template <bool BATCHED, typename T, int MODE, int LB, int NW, typename Args>
-int launch_coeff_nb(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
-  switch (p.nb) {
-    case 9: return launch_coeff_t<BATCHED, T, LB, 9, 4, MODE, NW>(p, a, grid, st);
-    case 11: return launch_coeff_t<BATCHED, T, LB, 11, 4, MODE, NW>(p, a, grid, st);
-    default: return launch_coeff_t<BATCHED, T, LB, 12, 4, MODE, NW>(p, a, grid, st);
-  }
-}
-
-// particle groups per tile: only the small cutoff buckets have the LDS for 128 or 256
-// particles per tile
-template <bool BATCHED, typename T, int MODE, int LB, typename Args>
-int launch_coeff_nw(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
-  if constexpr (LB <= 6) {
-    if (p.nw == 1) return launch_coeff_nb<BATCHED, T, MODE, LB, 1>(p, a, grid, st);
-    if (p.nw == 2) return launch_coeff_nb<BATCHED, T, MODE, LB, 2>(p, a, grid, st);
-  }
-  return launch_coeff_nb<BATCHED, T, MODE, LB, 4>(p, a, grid, st);
-}
-
-template <bool BATCHED, typename Args>
-int launch_coeff_any(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
-  const int mode = p.prec == ETICS_FP64 ? 0 : (p.prec == ETICS_MIXED_FP64ACC ? 1 : 2);
-#define ETICS_LB_CASES(T, MODE)                                                  \
-  switch (p.lb) {                                                                \
-    case 2: return launch_coeff_nw<BATCHED, T, MODE, 2>(p, a, grid, st);         \
-    case 6: return launch_coeff_nw<BATCHED, T, MODE, 6>(p, a, grid, st);         \
-    case 10: return launch_coeff_nw<BATCHED, T, MODE, 10>(p, a, grid, st);       \
-    default: return launch_coeff_nw<BATCHED, T, MODE, 14>(p, a, grid, st);       \
-  }
-  if (mode == 0) {
-    ETICS_LB_CASES(double, 0)
-  } else if (mode == 1) {
-    ETICS_LB_CASES(float, 0)
-  } else {
-    ETICS_LB_CASES(float, 1)
-  }
-#undef ETICS_LB_CASES
-}
-
-void fill_scale(double* scale, int nmax, int lmax) {
+void fill_scale(double* scale, int nmax, int lmax, int basis) {
   for (int nn = 0; nn <= nmax; ++nn)
     for (int l = 0; l <= lmax; ++l)
-      scale[nn * (lmax + 1) + l] = -2.0 * std::sqrt(kPi) * anl_tilde(nn, l) * gegen_k(nn, 2.0 * l + 1.5);
+      scale[nn * (lmax + 1) + l] =
+          -2.0 * std::sqrt(kPi) * anl_tilde(nn, l, basis) * gegen_k(nn, basis_alpha(basis, l));
 }
 
 }  // namespace
 
 // ------------------------------------------------------------------ planning
-bool make_coeff_plan(int64_t n, int nmax, int lmax, int prec, CoeffPlan* p) {
+namespace {
+
+// LDS bytes per particle of a tile, and the element size, of a plan's cutoff bucket
+size_t plan_per_particle(const CoeffPlan& q) {
+  return size_t(q.spg + q.spz) * (q.prec == ETICS_FP64 ? 8 : 4);
+}
+
+// Complete a plan from its tile shape (nw particle groups, tp particles, streams); false
+// if the shape breaks a limit of the kernel: phase 1 has one lane per particle in each
+// of 4/nw groups of 64, phase 2 needs streams x nblocks lanes, and the tile and the
+// stream merge must fit the LDS.
+bool finish_plan(CoeffPlan& q, int nw, int tp, int streams) {
+  if (!(nw == 4 || ((nw == 1 || nw == 2) && q.lb <= 6))) return false;
+  if (streams < 1 || streams > kMaxStreams || streams * q.nblocks > kCoeffThreads) return false;
+  if (tp < 1 || tp > 64 * (4 / nw)) return false;
+  const size_t lds = size_t(tp) * plan_per_particle(q);
+  const size_t merge_bytes = size_t(q.nblocks) * q.nb * q.bs * 8;
+  q.nw = nw;
+  q.tp = tp;
+  q.streams = streams;
+  q.lds_bytes = lds > merge_bytes ? lds : merge_bytes;
+  if (q.lds_bytes > 160 * 1024) return false;
+  // FP32 runs of about 72 particles per lane before each fold
+  const int per_tile = q.tp / q.streams > 0 ? q.tp / q.streams : 1;
+  q.flush_tiles = 72 / per_tile > 0 ? 72 / per_tile : 1;
+  return true;
+}
+
+}  // namespace
+
+int coeff_grid(const CoeffPlan& p, int64_t work_items) {
+  int64_t grid = int64_t(256) * p.grid_mult;
+  if (grid > work_items) grid = work_items;
+  if (grid < 1) grid = 1;
+  return int(grid);
+}
+
+bool make_coeff_plan(int64_t n, int nmax, int lmax, int prec, CoeffPlan* p, int basis, bool batched) {
   CoeffPlan q{};
   q.nmax = nmax;
   q.lmax = lmax;
   q.prec = prec;
+  q.basis = basis;
   const size_t esz = prec == ETICS_FP64 ? 8 : 4;
   q.lb = lmax <= 2 ? 2 : lmax <= 6 ? 6 : lmax <= 10 ? 10 : 14;
   q.nb = nmax + 1 <= 9 ? 9 : nmax + 1 <= 11 ? 11 : 12;
@@ -763,44 +187,52 @@ bool make_coeff_plan(int64_t n, int nmax, int lmax, int prec, CoeffPlan* p) {
   q.nblocks = 0;
   for (int l = 0; l <= lmax; ++l) q.nblocks += q.nchunks * slot_pad(l, q.bs) / q.bs;
   if (q.nblocks > kCoeffThreads) return false;
-  q.streams = kCoeffThreads / q.nblocks;
-  if (q.streams > kMaxStreams) q.streams = kMaxStreams;
-  // particles per tile: one per lane of a wavefront in each particle group (1, 2 or 4
-  // groups of 64, the four wavefronts splitting the basis jobs 4, 2 or 1 ways), a
-  // multiple of the stream count (every stream takes the same number), within the LDS
-  // budget; more groups when they fit (small cutoffs), so a tile does more work per
-  // barrier
+  // Fixed rules.  Streams: as many copies of the register blocks as the workgroup's
+  // lanes hold.  Particles per tile: one per lane of a wavefront in each particle group
+  // (1, 2 or 4 groups of 64, the four wavefronts splitting the basis jobs 4, 2 or 1
+  // ways), a multiple of the stream count (every stream takes the same number), within
+  // the LDS budget; more groups when they fit (small cutoffs), so a tile does more work
+  // per barrier.  Two workgroups per CU when the LDS allows it in FP32.
+  int streams = kCoeffThreads / q.nblocks;
+  if (streams > kMaxStreams) streams = kMaxStreams;
   const size_t budget = esz == 4 ? 76 * 1024 : 150 * 1024;
-  const size_t per_particle = size_t(q.spg + q.spz) * esz;
-  q.nw = 4;
-  int tp = 64;
+  const size_t per_particle = plan_per_particle(q);
+  int nw = 4, tp = 64;
   if (q.lb <= 6) {
-    for (int nw = 1; nw <= 2; nw *= 2) {
-      const int tmax = 64 * (4 / nw);
-      if (size_t(tmax) * per_particle <= budget && q.streams <= tmax) {
-        q.nw = nw;
+    for (int w = 1; w <= 2; w *= 2) {
+      const int tmax = 64 * (4 / w);
+      if (size_t(tmax) * per_particle <= budget && streams <= tmax) {
+        nw = w;
         tp = tmax;
         break;
       }
     }
   }
   if (size_t(tp) * per_particle > budget) tp = int(budget / per_particle);
-  if (q.streams <= tp) tp = tp / q.streams * q.streams;
-  if (tp < 1) return false;
-  q.tp = tp;
-  q.lds_bytes = size_t(q.tp) * per_particle;
-  const size_t merge_bytes = size_t(q.nblocks) * q.nb * q.bs * 8;
-  if (merge_bytes > q.lds_bytes) q.lds_bytes = merge_bytes;
-  if (q.lds_bytes > 160 * 1024) return false;
-  // FP32 runs of about 72 particles per lane before each fold
-  const int per_tile = q.tp / q.streams > 0 ? q.tp / q.streams : 1;
-  q.flush_tiles = 72 / per_tile > 0 ? 72 / per_tile : 1;
+  if (streams <= tp) tp = tp / streams * streams;
+  if (!finish_plan(q, nw, tp, streams)) return false;
+  q.grid_mult = (esz == 4 && q.lds_bytes <= 80 * 1024) ? 2 : 1;
+  q.unit = kUnitParticles;
+  q.split = kForceSplit;
+  q.tuned = false;
+  // a plan measured faster by the tuner, if one is known and valid for this kernel
+  TunedParams t;
+  if (tuned_lookup(batched ? 1 : 0, nmax, lmax, prec, basis, n, &t)) {
+    CoeffPlan r = q;
+    bool ok = finish_plan(r, t.nw > 0 ? t.nw : q.nw, t.tp > 0 ? t.tp : q.tp,
+                          t.streams > 0 ? t.streams : q.streams);
+    if (t.grid_mult > 0) r.grid_mult = t.grid_mult;
+    if (t.unit > 0) r.unit = t.unit;
+    if (t.split > 0) r.split = t.split;
+    ok = ok && r.grid_mult >= 1 && r.grid_mult <= 2 && r.unit >= kMinUnitParticles &&
+         r.unit <= kMaxUnitParticles && r.split >= 1 && r.split <= 16 && r.unit / r.split >= 64;
+    if (ok) {
+      r.tuned = true;
+      q = r;
+    }
+  }
   const int64_t ntiles = (n + q.tp - 1) / q.tp;
-  const int wg_per_cu = (esz == 4 && q.lds_bytes <= 80 * 1024) ? 2 : 1;
-  int64_t grid = int64_t(256) * wg_per_cu;
-  if (grid > ntiles) grid = ntiles;
-  if (grid < 1) grid = 1;
-  q.grid = int(grid);
+  q.grid = coeff_grid(q, ntiles);
   *p = q;
   return true;
 }
@@ -810,10 +242,28 @@ size_t coeff_partials_bytes(const CoeffPlan& p) {
   return size_t(p.grid) * 2 * K * 8;  // FP64 or a double-float pair: 8 bytes per entry
 }
 
-int launch_scf_coeffs(const CoeffPlan& p, const double* x, const double* y, const double* z,
-                      const double* m, int64_t n, double* A, double* B, void* ws,
-                      hipStream_t st) {
+int launch_coeff_reduce(const CoeffPlan& p, const void* partials, int grid, double* A, double* B,
+                        hipStream_t st) {
   const int K = coeff_count(p.nmax, p.lmax);
+  ReduceArgs r{};
+  r.partials = partials;
+  r.A = A;
+  r.B = B;
+  r.grid = grid;
+  r.K = K;
+  r.nmax = p.nmax;
+  r.lmax = p.lmax;
+  fill_scale(r.scale, p.nmax, p.lmax, p.basis);
+  const int rb = (2 * K + kRedCols - 1) / kRedCols;
+  if (p.prec == ETICS_MIXED_COMP32)
+    hipLaunchKernelGGL(scf_reduce_kernel<1>, dim3(rb), dim3(256), 0, st, r);
+  else
+    hipLaunchKernelGGL(scf_reduce_kernel<0>, dim3(rb), dim3(256), 0, st, r);
+  return hip_fail(hipGetLastError(), "scf_reduce_kernel launch");
+}
+
+CoeffArgs coeff_args(const CoeffPlan& p, const double* x, const double* y, const double* z,
+                     const double* m, int64_t n, int tile_particles, void* ws) {
   CoeffArgs a{};
   a.x = x;
   a.y = y;
@@ -821,35 +271,35 @@ int launch_scf_coeffs(const CoeffPlan& p, const double* x, const double* y, cons
   a.m = m;
   a.n = n;
   a.partials = ws;
-  a.K = K;
+  a.K = coeff_count(p.nmax, p.lmax);
   a.nmax = p.nmax;
   a.lmax = p.lmax;
   a.tp = p.tp;
   a.nblocks = p.nblocks;
   a.streams = p.streams;
   a.flush_tiles = p.flush_tiles;
-  a.ntiles = int((n + p.tp - 1) / p.tp);
+  a.ntiles = int((n + tile_particles - 1) / tile_particles);
   a.nchunks = p.nchunks;
+  return a;
+}
 
-  const int mode = p.prec == ETICS_FP64 ? 0 : (p.prec == ETICS_MIXED_FP64ACC ? 1 : 2);
-  int rc = launch_coeff_any<false>(p, a, p.grid, st);
+int launch_scf_coeffs(const CoeffPlan& p, const double* x, const double* y, const double* z,
+                      const double* m, int64_t n, double* A, double* B, void* ws,
+                      hipStream_t st) {
+  const CoeffArgs a = coeff_args(p, x, y, z, m, n, p.tp, ws);
+  int rc = launch_coeff_any<false, false>(p, a, p.grid, st);
   if (rc) return rc;
+  return launch_coeff_reduce(p, ws, p.grid, A, B, st);
+}
 
-  ReduceArgs r{};
-  r.partials = ws;
-  r.A = A;
-  r.B = B;
-  r.grid = p.grid;
-  r.K = K;
-  r.nmax = p.nmax;
-  r.lmax = p.lmax;
-  fill_scale(r.scale, p.nmax, p.lmax);
-  const int rb = (2 * K + kRedCols - 1) / kRedCols;
-  if (mode == 2)
-    hipLaunchKernelGGL(scf_reduce_kernel<1>, dim3(rb), dim3(256), 0, st, r);
-  else
-    hipLaunchKernelGGL(scf_reduce_kernel<0>, dim3(rb), dim3(256), 0, st, r);
-  return hip_fail(hipGetLastError(), "scf_reduce_kernel launch");
+bool dot_plan(const CoeffPlan& p, int64_t n, CoeffPlan* out) {
+  CoeffPlan q = p;
+  int tp = p.tp / 2 * 2;
+  if (tp < p.streams) tp = (p.streams + 1) / 2 * 2;
+  if (!finish_plan(q, p.nw, tp, p.streams)) return false;
+  q.grid = coeff_grid(q, (n + q.tp / 2 - 1) / (q.tp / 2));
+  *out = q;
+  return true;
 }
 
 // ------------------------------------------------------- allocation-free variant
@@ -933,15 +383,33 @@ __global__ __launch_bounds__(256) void scf_reduce_batched_kernel(const BatchedRe
   }
 }
 
-int max_units(int64_t ntotal, int nsys) {
-  return nsys + int((ntotal + kUnitParticles - 1) / kUnitParticles);
+int max_units(int64_t ntotal, int nsys, int unit) {
+  return nsys + int((ntotal + unit - 1) / unit);
 }
 
-int launch_scf_coeffs_batched(const CoeffPlan& p, const double* x, const double* y, const double* z,
-                              const double* m, const int64_t* offsets, const int* ustart,
-                              const int* usys, int nsys, int64_t ntotal, double* A, double* B,
-                              void* partials, hipStream_t st) {
-  const int K = coeff_count(p.nmax, p.lmax);
+int launch_coeff_reduce_batched(const CoeffPlan& p, const void* partials, const int* ustart, int nsys,
+                                double* A, double* B, hipStream_t st) {
+  BatchedReduceArgs r{};
+  r.partials = partials;
+  r.ustart = ustart;
+  r.A = A;
+  r.B = B;
+  r.nsys = nsys;
+  r.K = coeff_count(p.nmax, p.lmax);
+  r.nmax = p.nmax;
+  r.lmax = p.lmax;
+  fill_scale(r.scale, p.nmax, p.lmax, kBasisHO);
+  if (p.prec == ETICS_MIXED_COMP32)
+    hipLaunchKernelGGL(scf_reduce_batched_kernel<1>, dim3(nsys), dim3(256), 0, st, r);
+  else
+    hipLaunchKernelGGL(scf_reduce_batched_kernel<0>, dim3(nsys), dim3(256), 0, st, r);
+  return hip_fail(hipGetLastError(), "scf_reduce_batched_kernel launch");
+}
+
+BatchedCoeffArgs batched_coeff_args(const CoeffPlan& p, const double* x, const double* y,
+                                    const double* z, const double* m, const int64_t* offsets,
+                                    const int* ustart, const int* usys, int nsys, int64_t ntotal,
+                                    void* partials) {
   BatchedCoeffArgs a{};
   a.x = x;
   a.y = y;
@@ -953,7 +421,7 @@ int launch_scf_coeffs_batched(const CoeffPlan& p, const double* x, const double*
   a.ntotal = ntotal;
   a.partials = partials;
   a.nsys = nsys;
-  a.K = K;
+  a.K = coeff_count(p.nmax, p.lmax);
   a.nmax = p.nmax;
   a.lmax = p.lmax;
   a.tp = p.tp;
@@ -961,27 +429,19 @@ int launch_scf_coeffs_batched(const CoeffPlan& p, const double* x, const double*
   a.streams = p.streams;
   a.nchunks = p.nchunks;
   a.flush_tiles = p.flush_tiles;
-  const int wg_per_cu = (p.prec != ETICS_FP64 && p.lds_bytes <= 80 * 1024) ? 2 : 1;
-  int grid = 256 * wg_per_cu;
-  const int mu = max_units(ntotal, nsys);
-  if (grid > mu) grid = mu;
-  int rc = launch_coeff_any<true>(p, a, grid, st);
+  a.unit = p.unit;
+  return a;
+}
+
+int launch_scf_coeffs_batched(const CoeffPlan& p, const double* x, const double* y, const double* z,
+                              const double* m, const int64_t* offsets, const int* ustart,
+                              const int* usys, int nsys, int64_t ntotal, double* A, double* B,
+                              void* partials, hipStream_t st) {
+  const BatchedCoeffArgs a = batched_coeff_args(p, x, y, z, m, offsets, ustart, usys, nsys, ntotal, partials);
+  const int grid = coeff_grid(p, max_units(ntotal, nsys, p.unit));
+  int rc = launch_coeff_any<true, false>(p, a, grid, st);
   if (rc) return rc;
-  BatchedReduceArgs r{};
-  r.partials = partials;
-  r.ustart = ustart;
-  r.A = A;
-  r.B = B;
-  r.nsys = nsys;
-  r.K = K;
-  r.nmax = p.nmax;
-  r.lmax = p.lmax;
-  fill_scale(r.scale, p.nmax, p.lmax);
-  if (p.prec == ETICS_MIXED_COMP32)
-    hipLaunchKernelGGL(scf_reduce_batched_kernel<1>, dim3(nsys), dim3(256), 0, st, r);
-  else
-    hipLaunchKernelGGL(scf_reduce_batched_kernel<0>, dim3(nsys), dim3(256), 0, st, r);
-  return hip_fail(hipGetLastError(), "scf_reduce_batched_kernel launch");
+  return launch_coeff_reduce_batched(p, partials, ustart, nsys, A, B, st);
 }
 
 }  // namespace etics

@@ -26,6 +26,8 @@ ETICS_POT = 1
 ETICS_ACC = 2
 ETICS_POT_ACC = 3
 ETICS_LEAPFROG_EAGER = 1
+ETICS_BASIS_HO = 0
+ETICS_BASIS_CB = 1
 ETICS_NMAX_CAP = 20
 ETICS_LMAX_CAP = 14
 
@@ -34,8 +36,11 @@ PRECISIONS = {"fp64": ETICS_FP64, "mixed": ETICS_MIXED_FP64ACC, "comp32": ETICS_
 EXPORTED = [
     "etics_coeff_count", "etics_scf_workspace_size", "etics_scf_coeffs", "etics_scf_force",
     "etics_mex_workspace_size", "etics_mex_force", "etics_batched_workspace_size",
-    "etics_scf_coeffs_noalloc", "etics_scf_coeffs_batched", "etics_scf_force_batched", "etics_leapfrog_scf_batched",
+    "etics_scf_coeffs_noalloc", "etics_scf_coeffs_basis", "etics_scf_force_basis",
+    "etics_scf_coeffs_batched", "etics_scf_force_batched", "etics_leapfrog_scf_batched",
     "etics_direct_force", "etics_set_timing_events", "etics_last_error", "etics_version",
+    "etics_tuning_load", "etics_tuning_set", "etics_tuning_clear", "etics_plan_info",
+    "etics_scf_coeffs_dot", "etics_scf_jerk", "etics_hermite_workspace_size", "etics_hermite_scf_batched",
 ]
 
 
@@ -67,6 +72,29 @@ def lib():
         L.etics_scf_coeffs.restype = _int
         L.etics_scf_coeffs_noalloc.argtypes = [_vp, _vp, _vp, _vp, _i64, _int, _int, _int, _vp, _vp, _vp]
         L.etics_scf_coeffs_noalloc.restype = _int
+        L.etics_scf_coeffs_basis.argtypes = [_vp, _vp, _vp, _vp, _i64, _int, _int, _int, _int, _vp, _vp,
+                                             _vp, _sz, _vp]
+        L.etics_scf_coeffs_basis.restype = _int
+        L.etics_scf_force_basis.argtypes = [_vp, _vp, _vp, _i64, _int, _int, _vp, _vp, _int, _int, _int,
+                                            _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.etics_scf_force_basis.restype = _int
+        L.etics_tuning_load.argtypes = [ctypes.c_char_p]
+        L.etics_tuning_load.restype = _int
+        L.etics_tuning_set.argtypes = [_int, _int, _int, _int, _int, _i64, ctypes.POINTER(_int), _int]
+        L.etics_tuning_set.restype = _int
+        L.etics_tuning_clear.argtypes = []
+        L.etics_tuning_clear.restype = _int
+        L.etics_plan_info.argtypes = [_int, _i64, _int, _int, _int, _int, ctypes.POINTER(_int), _int]
+        L.etics_plan_info.restype = _int
+        L.etics_scf_coeffs_dot.argtypes = [_vp] * 7 + [_i64, _int, _int, _int, _vp, _vp, _vp, _sz, _vp]
+        L.etics_scf_coeffs_dot.restype = _int
+        L.etics_scf_jerk.argtypes = [_vp] * 6 + [_i64, _int, _int] + [_vp] * 4 + [_int] + [_vp] * 7 + [_sz, _vp]
+        L.etics_scf_jerk.restype = _int
+        L.etics_hermite_workspace_size.argtypes = [_i64, _int, _int, _int, _int]
+        L.etics_hermite_workspace_size.restype = _sz
+        L.etics_hermite_scf_batched.argtypes = [_vp] * 8 + [_int, _i64, _int, _int, _int, ctypes.c_double, _int,
+                                                            _int, _vp, _sz, _vp]
+        L.etics_hermite_scf_batched.restype = _int
         L.etics_scf_force.argtypes = [_vp, _vp, _vp, _i64, _int, _int, _vp, _vp, _int, _int,
                                       _vp, _vp, _vp, _vp, _vp, _sz, _vp]
         L.etics_scf_force.restype = _int
@@ -184,6 +212,37 @@ def etics_set_timing_events(before, after) -> None:
     _check(lib().etics_set_timing_events(hb, ha))
 
 
+PLAN_FIELDS = ("nw", "tp", "streams", "grid_mult", "unit", "split")
+
+
+def etics_tuning_load(path: str) -> int:
+    """Replace the library's tuned-plan table with the plans of a JSON file."""
+    rc = lib().etics_tuning_load(os.fsencode(path))
+    _check(rc if rc < 0 else 0)
+    return rc
+
+
+def etics_tuning_set(nmax: int, lmax: int, precision, n: int, plan: dict, batched=False,
+                     basis=ETICS_BASIS_HO) -> None:
+    """Add or replace one tuned plan (missing fields keep the fixed rules' values)."""
+    vals = (_int * 6)(*[int(plan.get(k, 0)) for k in PLAN_FIELDS])
+    _check(lib().etics_tuning_set(int(bool(batched)), nmax, lmax, _prec(precision), int(basis), int(n), vals, 6))
+
+
+def etics_tuning_clear() -> None:
+    _check(lib().etics_tuning_clear())
+
+
+def etics_plan_info(n: int, nmax: int, lmax: int, precision, batched=False, basis=ETICS_BASIS_HO) -> dict:
+    """The tile plan a coefficient call over n particles would use."""
+    out = (_int * 8)()
+    _check(lib().etics_plan_info(int(bool(batched)), int(n), nmax, lmax, _prec(precision), int(basis), out, 8))
+    d = dict(zip(PLAN_FIELDS, out[:6]))
+    d["tuned"] = bool(out[6])
+    d["grid"] = out[7]
+    return d
+
+
 def etics_coeff_count(nmax: int, lmax: int) -> int:
     return lib().etics_coeff_count(nmax, lmax)
 
@@ -294,6 +353,45 @@ def etics_scf_force(x, y, z, nmax: int, lmax: int, A, B, precision=ETICS_MIXED_F
     return pot, ax, ay, az
 
 
+def etics_scf_coeffs_basis(x, y, z, m, nmax: int, lmax: int, precision=ETICS_MIXED_FP64ACC,
+                           basis=ETICS_BASIS_HO, A=None, B=None, ws=None, stream=None):
+    """SCF coefficients (A, B) in radial basis `basis` (ETICS_BASIS_HO or ETICS_BASIS_CB)."""
+    p = _prec(precision)
+    n, device = _first_tensor(x)
+    K = _coeff_count_checked(nmax, lmax)
+    need = etics_scf_workspace_size(n, nmax, lmax, p)
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (m, "m", n, F64, True), (A, "A", K, F64, False), (B, "B", K, F64, False),
+               (ws, "ws", need, None, False)])
+    A = torch.empty(K, dtype=F64, device=device) if A is None else A
+    B = torch.empty(K, dtype=F64, device=device) if B is None else B
+    ws = workspace(need, device) if ws is None else ws
+    _check(lib().etics_scf_coeffs_basis(_ptr(x), _ptr(y), _ptr(z), _ptr(m), n, nmax, lmax, p, int(basis),
+                                        _ptr(A), _ptr(B), _ptr(ws), _nbytes(ws), _stream(stream)))
+    return A, B
+
+
+def etics_scf_force_basis(x, y, z, nmax: int, lmax: int, A, B, precision=ETICS_MIXED_FP64ACC,
+                          basis=ETICS_BASIS_HO, outputs=ETICS_POT_ACC, pot=None, ax=None, ay=None, az=None,
+                          ws=None, stream=None):
+    """SCF potential and acceleration from coefficients A, B of radial basis `basis`."""
+    p = _prec(precision)
+    n, device = _first_tensor(x)
+    K = _coeff_count_checked(nmax, lmax)
+    need = etics_scf_workspace_size(n, nmax, lmax, p)
+    if A is None or B is None:
+        raise TypeError("A and B are required")
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (A, "A", K, F64, False), (B, "B", K, F64, False), (ws, "ws", need, None, False)]
+              + _out_items(outputs, n, pot, ax, ay, az))
+    pot, ax, ay, az = _outputs(outputs, n, device, pot, ax, ay, az)
+    ws = workspace(need, device) if ws is None else ws
+    _check(lib().etics_scf_force_basis(_ptr(x), _ptr(y), _ptr(z), n, nmax, lmax, _ptr(A), _ptr(B), p,
+                                       int(basis), outputs, _ptr(pot), _ptr(ax), _ptr(ay), _ptr(az),
+                                       _ptr(ws), _nbytes(ws), _stream(stream)))
+    return pot, ax, ay, az
+
+
 def etics_mex_force(x, y, z, m, lmax: int, precision=ETICS_MIXED_FP64ACC, outputs=ETICS_POT_ACC,
                     pot=None, ax=None, ay=None, az=None, ws=None, stream=None):
     """MEX potential and acceleration of every particle from all the others."""
@@ -393,3 +491,67 @@ def etics_leapfrog_scf_batched(x, y, z, vx, vy, vz, m, offsets, nmax: int, lmax:
     _check(lib().etics_leapfrog_scf_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz),
                                             _ptr(m), _ptr(offsets), nsys, n, nmax, lmax, p, float(dt),
                                             int(nsteps), int(flags), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def etics_scf_coeffs_dot(x, y, z, vx, vy, vz, m, nmax: int, lmax: int, precision=ETICS_MIXED_FP64ACC,
+                         Adot=None, Bdot=None, ws=None, stream=None):
+    """Time derivatives dA/dt, dB/dt of the coefficients along the velocities."""
+    p = _prec(precision)
+    n, device = _first_tensor(x)
+    K = _coeff_count_checked(nmax, lmax)
+    need = etics_scf_workspace_size(n, nmax, lmax, p)
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (vx, "vx", n, F64, True), (vy, "vy", n, F64, True), (vz, "vz", n, F64, True),
+               (m, "m", n, F64, True), (Adot, "Adot", K, F64, False), (Bdot, "Bdot", K, F64, False),
+               (ws, "ws", need, None, False)])
+    Adot = torch.empty(K, dtype=F64, device=device) if Adot is None else Adot
+    Bdot = torch.empty(K, dtype=F64, device=device) if Bdot is None else Bdot
+    ws = workspace(need, device) if ws is None else ws
+    _check(lib().etics_scf_coeffs_dot(_ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), _ptr(m), n, nmax,
+                                      lmax, p, _ptr(Adot), _ptr(Bdot), _ptr(ws), _nbytes(ws), _stream(stream)))
+    return Adot, Bdot
+
+
+def etics_scf_jerk(x, y, z, vx, vy, vz, nmax: int, lmax: int, A, B, Adot, Bdot, precision=ETICS_MIXED_FP64ACC,
+                   out=None, ws=None, stream=None):
+    """Acceleration and jerk (ax, ay, az, jx, jy, jz) at points moving with (vx, vy, vz)."""
+    p = _prec(precision)
+    n, device = _first_tensor(x)
+    K = _coeff_count_checked(nmax, lmax)
+    need = etics_scf_workspace_size(n, nmax, lmax, p)
+    out = [None] * 6 if out is None else list(out)
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (vx, "vx", n, F64, True), (vy, "vy", n, F64, True), (vz, "vz", n, F64, True),
+               (A, "A", K, F64, False), (B, "B", K, F64, False), (Adot, "Adot", K, F64, False),
+               (Bdot, "Bdot", K, F64, False), (ws, "ws", need, None, False)]
+              + [(o, f"out[{k}]", n, F64, False) for k, o in enumerate(out)])
+    out = [torch.empty(n, dtype=F64, device=device) if o is None else o for o in out]
+    ws = workspace(need, device) if ws is None else ws
+    _check(lib().etics_scf_jerk(_ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), n, nmax, lmax, _ptr(A),
+                                _ptr(B), _ptr(Adot), _ptr(Bdot), p, *[_ptr(o) for o in out], _ptr(ws), _nbytes(ws),
+                                _stream(stream)))
+    return tuple(out)
+
+
+def etics_hermite_workspace_size(ntotal: int, nsys: int, nmax: int, lmax: int,
+                                 precision=ETICS_MIXED_FP64ACC) -> int:
+    return lib().etics_hermite_workspace_size(ntotal, nsys, nmax, lmax, _prec(precision))
+
+
+def etics_hermite_scf_batched(x, y, z, vx, vy, vz, m, offsets, nmax: int, lmax: int, dt: float,
+                              nsteps: int, precision=ETICS_MIXED_FP64ACC, flags: int = 0, ws=None,
+                              stream=None):
+    """Advance x..vz in place by nsteps fourth-order Hermite steps (one captured graph replayed)."""
+    p = _prec(precision)
+    n, device = _first_tensor(x)
+    nsys = _nsys_of(offsets)
+    _coeff_count_checked(nmax, lmax)
+    need = etics_hermite_workspace_size(n, nsys, nmax, lmax, p)
+    _validate([(x, "x", n, F64, True), (y, "y", n, F64, True), (z, "z", n, F64, True),
+               (vx, "vx", n, F64, True), (vy, "vy", n, F64, True), (vz, "vz", n, F64, True),
+               (m, "m", n, F64, True), (offsets, "offsets", nsys + 1, I64, True),
+               (ws, "ws", need, None, False)])
+    ws = workspace(need, device) if ws is None else ws
+    _check(lib().etics_hermite_scf_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), _ptr(m),
+                                           _ptr(offsets), nsys, n, nmax, lmax, p, float(dt), int(nsteps),
+                                           int(flags), _ptr(ws), _nbytes(ws), _stream(stream)))

@@ -78,6 +78,15 @@ def triaxial_hernquist(n, seed, axes=(1.0, 0.8, 0.6)):
                      meta={"model": "triaxial_hernquist", "axes": list(axes), "seed": seed})
 
 
+def triaxial_plummer(n, seed, b=1.0, axes=(1.0, 0.8, 0.6)):
+    """Plummer sphere (scale b, m = 1/n) with x, y, z scaled by axes: the cored model
+    that the Clutton-Brock radial basis expands from its zeroth order."""
+    rng = np.random.default_rng(seed)
+    x, y, z = sphere(rng, n, "plummer", b)
+    return Particles(x * axes[0], y * axes[1], z * axes[2], np.full(n, 1.0 / n),
+                     meta={"model": "triaxial_plummer", "b": b, "axes": list(axes), "seed": seed})
+
+
 def hernquist_plummer_offset(n, seed, b=0.3, offset=(0.5, 0.0, 0.0)):
     """Config 3 form: n/2 Hernquist (a=1) at the origin + n/2 Plummer (b) centred at offset."""
     rng = np.random.default_rng(seed)
