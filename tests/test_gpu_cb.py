@@ -1,0 +1,133 @@
+"""GPU parity of the SCF path in the Clutton-Brock radial basis (Section 2.5)
+against the FP64 CPU oracle in the same basis, through the C-ABI."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_1406_4254_amd import accuracy as acc  # noqa: E402
+from paper_1406_4254_amd import workloads as W  # noqa: E402
+
+FP64, MIXED, COMP32 = 0, 1, 2
+CB = 1
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1406_4254_amd import etics
+    etics.lib()
+    return etics
+
+
+def dev(*arrs):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in arrs]
+
+
+def gpu_coeffs(E, p, nmax, lmax, prec):
+    x, y, z, m = dev(p.x, p.y, p.z, p.m)
+    A, B = E.etics_scf_coeffs_basis(x, y, z, m, nmax, lmax, prec, CB)
+    return A.cpu().numpy(), B.cpu().numpy()
+
+
+def gpu_force(E, p, nmax, lmax, A, B, prec, outputs=3):
+    x, y, z = dev(p.x, p.y, p.z)
+    dA, dB = dev(A, B)
+    r = E.etics_scf_force_basis(x, y, z, nmax, lmax, dA, dB, prec, CB, outputs)
+    return [None if t is None else t.cpu().numpy() for t in r]
+
+
+def report(tag, e):
+    s = acc.summarize(e)
+    print(f"{tag}: median {s['median']:.3e} p99 {s['p99']:.3e} max {s['max']:.3e}", flush=True)
+    return s
+
+
+@pytest.mark.parametrize("nmax,lmax", [(10, 6), (0, 0), (2, 1), (4, 4), (3, 7), (10, 10), (20, 14)])
+def test_cb_fp64_coeffs_match_oracle(E, orc, nmax, lmax):
+    p = W.triaxial_plummer(3001, 11)  # several tiles and a ragged tail
+    A, B = gpu_coeffs(E, p, nmax, lmax, FP64)
+    rA, rB = orc.scf_coeffs(p.x, p.y, p.z, p.m, nmax, lmax, basis=CB)
+    e = acc.coeff_errors(A, B, rA, rB)
+    print(f"cb ({nmax},{lmax}) coeff {e}", flush=True)
+    # measured at most 3.8e-15 (at (20,14))
+    assert e["norm_rel"] < 4e-14 and e["max_rel_to_max"] < 4e-14
+
+
+@pytest.mark.parametrize("nmax,lmax", [(10, 6), (2, 1), (4, 4), (10, 10), (20, 14)])
+def test_cb_fp64_force_match_oracle(E, orc, nmax, lmax):
+    p = W.triaxial_plummer(2500, 12)
+    rA, rB = orc.scf_coeffs(p.x, p.y, p.z, p.m, nmax, lmax, basis=CB)
+    pot, ax, ay, az = gpu_force(E, p, nmax, lmax, rA, rB, FP64)
+    pot1 = gpu_force(E, p, nmax, lmax, rA, rB, FP64, outputs=1)[0]
+    rp, rx, ry, rz = orc.scf_force(p.x, p.y, p.z, nmax, lmax, rA, rB, basis=CB)
+    ef = report(f"cb fp64 force ({nmax},{lmax})", acc.force_rel_err(ax, ay, az, rx, ry, rz))
+    ep = report(f"cb fp64 pot ({nmax},{lmax})", acc.pot_rel_err(pot, rp))
+    ep1 = report(f"cb fp64 pot-only ({nmax},{lmax})", acc.pot_rel_err(pot1, rp))
+    # measured at most 2.4e-14 (force) and 1.2e-14 (potential), at (20,14)
+    assert ef["max"] < 2.5e-13 and ep["max"] < 1.5e-13 and ep1["max"] < 1.5e-13
+
+
+@pytest.mark.parametrize("prec", [MIXED, COMP32])
+@pytest.mark.parametrize("n,nmax,lmax", [(10_000, 10, 6), (30_000, 10, 10), (20_000, 20, 14)])
+def test_cb_mixed_force_accuracy(E, orc, prec, n, nmax, lmax):
+    """Mixed modes in the Clutton-Brock basis against the FP64 oracle: the same gate as
+    the Hernquist-Ostriker path (force median <= 1e-5, p99 <= 1e-4)."""
+    p = W.triaxial_plummer(n, 13)
+    A, B = gpu_coeffs(E, p, nmax, lmax, prec)
+    rA, rB = orc.scf_coeffs(p.x, p.y, p.z, p.m, nmax, lmax, basis=CB)
+    ce = acc.coeff_errors(A, B, rA, rB)
+    print(f"cb prec{prec} ({nmax},{lmax}) coeff {ce}", flush=True)
+    pot, ax, ay, az = gpu_force(E, p, nmax, lmax, A, B, prec)
+    pot1 = gpu_force(E, p, nmax, lmax, A, B, prec, outputs=1)[0]
+    rp, rx, ry, rz = orc.scf_force(p.x, p.y, p.z, nmax, lmax, rA, rB, basis=CB)
+    ef = report(f"cb prec{prec} ({nmax},{lmax}) force", acc.force_rel_err(ax, ay, az, rx, ry, rz))
+    ep = report(f"cb prec{prec} ({nmax},{lmax}) pot", acc.pot_rel_err(pot, rp))
+    ep1 = report(f"cb prec{prec} ({nmax},{lmax}) pot-only", acc.pot_rel_err(pot1, rp))
+    assert ce["norm_rel"] < 1e-5
+    assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4
+    for e in (ep, ep1):
+        assert e["median"] <= 1e-5 and e["p99"] <= 1e-4
+
+
+def test_cb_origin_axis_and_ragged(E, orc):
+    """Points at the origin, on the z axis and next to it, and sizes around a tile."""
+    p = W.triaxial_plummer(400, 14)
+    x, y, z = p.x.copy(), p.y.copy(), p.z.copy()
+    x[0] = y[0] = z[0] = 0.0
+    x[1] = y[1] = 0.0; z[1] = 0.7
+    x[2] = y[2] = 0.0; z[2] = -2.5
+    x[3], y[3], z[3] = 1e-7, -2e-7, 0.4
+    q = W.Particles(x, y, z, p.m)
+    nmax, lmax = 6, 6
+    rA, rB = orc.scf_coeffs(x, y, z, p.m, nmax, lmax, basis=CB)
+    A, B = gpu_coeffs(E, q, nmax, lmax, FP64)
+    assert acc.coeff_errors(A, B, rA, rB)["norm_rel"] < 1e-13
+    rp, rx, ry, rz = orc.scf_force(x, y, z, nmax, lmax, rA, rB, basis=CB)
+    for prec, tol in ((FP64, 1e-13), (MIXED, 1e-4)):
+        pot, ax, ay, az = gpu_force(E, q, nmax, lmax, rA, rB, prec)
+        assert np.all(np.isfinite(ax)) and np.all(np.isfinite(pot))
+        scale = np.max(np.sqrt(rx ** 2 + ry ** 2 + rz ** 2))
+        d = np.sqrt((ax - rx) ** 2 + (ay - ry) ** 2 + (az - rz) ** 2)
+        assert np.max(d[:4]) < tol * scale
+        assert np.max(acc.pot_rel_err(pot[:4], rp[:4])) < tol
+    for n in (1, 63, 64, 65, 4099):
+        s = W.triaxial_plummer(n, 15)
+        A, B = gpu_coeffs(E, s, 5, 4, FP64)
+        rA, rB = orc.scf_coeffs(s.x, s.y, s.z, s.m, 5, 4, basis=CB)
+        assert acc.coeff_errors(A, B, rA, rB)["norm_rel"] < 1e-13
+
+
+def test_cb_invalid_basis_rejected(E):
+    """A basis value other than the two radial bases is an error before any device work."""
+    import torch
+    p = W.triaxial_plummer(1000, 16)
+    x, y, z, m = dev(p.x, p.y, p.z, p.m)
+    with pytest.raises(E.EticsError):
+        E.etics_scf_coeffs_basis(x, y, z, m, 4, 4, FP64, 2)
+    A, B = E.etics_scf_coeffs_basis(x, y, z, m, 4, 4, FP64, CB)
+    with pytest.raises(E.EticsError):
+        E.etics_scf_force_basis(x, y, z, 4, 4, A, B, FP64, -1)
+    torch.cuda.synchronize()
