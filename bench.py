@@ -38,8 +38,8 @@ PEAK_HBM_GBS = 8000.0
 
 CSRC = os.path.join(ROOT, "paper_1406_4254_amd", "csrc")
 KERNEL_SOURCES = {
-    "coeff": ["etics_coeff.hip", "etics_device.hpp", "etics_tables.hpp"],
-    "force": ["etics_force.hip", "etics_device.hpp", "etics_tables.hpp"],
+    "coeff": ["etics_coeff.hip", "etics_coeff_wg.hpp", "etics_device.hpp", "etics_tables.hpp"],
+    "force": ["etics_force.hip", "etics_force_synth.hpp", "etics_device.hpp", "etics_tables.hpp"],
 }
 
 
@@ -88,6 +88,18 @@ def measured_traffic(which, workload):
     return rec["hbm_bytes_per_launch"]
 
 
+def cpu_model():
+    """CPU model name of the host (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def copy_calibration(torch, nbytes=256 << 20, reps=3):
     """Plain device-to-device copies of a known size; a counter run over this program
     reads them to scale the HBM byte counters."""
@@ -134,6 +146,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="mex,batched,hermite,potonly,cb,direct",
+                    help="comma list of the extra workloads to time (mex, batched, hermite, potonly, cb, direct)")
+    ap.add_argument("--lf-steps", type=int, default=100, help="leapfrog steps of the batched extra")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run plain 256 MiB device copies (for scaling byte counters)")
     args = ap.parse_args()
@@ -231,14 +246,14 @@ def main():
     fc, ff = flops_per_particle(nmax, lmax)
     # kernel names as the profiler prints them (template arguments: compute type, lmax
     # bucket, radial orders per register block, angular slots per block, accumulation
-    # mode, wavefronts per particle group)
+    # mode, wavefronts per particle group, radial basis)
+    plan = etics.etics_plan_info(n, nmax, lmax, etics.ETICS_MIXED_FP64ACC)
     lb_force = 2 if lmax <= 2 else (lmax + 1) // 2 * 2
     lb_coeff = 2 if lmax <= 2 else (6 if lmax <= 6 else (10 if lmax <= 10 else 14))
     nb = 9 if nmax + 1 <= 9 else (11 if nmax + 1 <= 11 else 12)
-    coeff_name = (f"scf_coeff_kernel<float, {lb_coeff}, {nb}, 4, 0, 4>" if lb_coeff >= 10
-                  else f"scf_coeff_kernel<float, {lb_coeff}, {nb}, 4, 0, nw>")
+    coeff_name = f"scf_coeff_kernel<float, {lb_coeff}, {nb}, 4, 0, {plan['nw']}, 0>"
     kernels = {
-        "force": (mixed["force_kernel_ms"], ff, f"scf_force_kernel<float, {lb_force}, true>"),
+        "force": (mixed["force_kernel_ms"], ff, f"scf_force_kernel<float, {lb_force}, true, 0>"),
         "coeff": (mixed["coeff_kernel_ms"], fc, coeff_name),
     }
     dom = max(kernels, key=lambda k: kernels[k][0])
@@ -270,7 +285,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "nmax": nmax, "lmax": lmax, "seed": 2,
-                   "axes": [1.0, 0.8, 0.6], "precision": "mixed: fp32 basis/synthesis, fp64 reduction"},
+                   "axes": [1.0, 0.8, 0.6], "precision": "mixed: fp32 basis/synthesis, fp64 reduction",
+                   "coeff_plan": plan},
         "stages_ms": {k: v for k, v in mixed.items() if k != "wall_s"},
         "step_tflops": step_tflops,
         "roofline": roofline,
@@ -282,7 +298,7 @@ def main():
         out["speedup_vs_fp64"] = value / fp64["value"]
 
     if not args.no_extras:
-        out["extras"] = extras(torch, np, etics, workloads, stream)
+        out["extras"] = extras(torch, np, etics, workloads, stream, set(args.extras.split(",")), args.lf_steps)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -291,10 +307,23 @@ def main():
         rA, rB = oracle.scf_coeffs(p.x, p.y, p.z, p.m, nmax, lmax)
         rp, rx, ry, rz = oracle.scf_force(p.x, p.y, p.z, nmax, lmax, rA, rB)
         cpu_s = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": n / cpu_s, "unit": "particles/s", "cores": oracle.num_threads(),
+        # one thread on a bounded sample of the same workload
+        ns = 200_000
+        nthr = oracle.num_threads()
+        oracle.set_threads(1)
+        t1 = time.perf_counter()
+        sA, sB = oracle.scf_coeffs(p.x[:ns], p.y[:ns], p.z[:ns], p.m[:ns], nmax, lmax)
+        oracle.scf_force(p.x[:ns], p.y[:ns], p.z[:ns], nmax, lmax, sA, sB)
+        one_s = time.perf_counter() - t1
+        oracle.set_threads(nthr)
+        out["cpu_baseline"] = {"value": n / cpu_s, "unit": "particles/s", "cores": nthr,
                                "kind": "oracle",
                                "sample": f"the full workload (N={n}, ({nmax},{lmax})), one force calculation "
-                                         f"(coefficients then potential and acceleration), {cpu_s:.2f} s"}
+                                         f"(coefficients then potential and acceleration), {cpu_s:.2f} s",
+                               "cpu_model": cpu_model(),
+                               "one_thread": {"value": ns / one_s, "unit": "particles/s", "cores": 1,
+                                              "sample": f"the first {ns} particles of the workload, one force "
+                                                        f"calculation, {one_s:.2f} s"}}
         A, B, pot, ax, ay, az = res
         ce = accuracy.coeff_errors(A, B, rA, rB)
         fe = accuracy.summarize(accuracy.force_rel_err(ax, ay, az, rx, ry, rz))
@@ -309,10 +338,27 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def extras(torch, np, etics, workloads, stream, reps=10):
-    """MEX force (N = 10^6, lmax = 10), the batched hipGraph leapfrog step and the FP64
-    direct summation of the accuracy study (N = 10^5)."""
+def extras(torch, np, etics, workloads, stream, which, lf_steps, reps=10):
+    """MEX force (N = 10^6, lmax = 10), the batched hipGraph leapfrog step, the
+    potential-only SCF step and the FP64 direct summation of the accuracy study
+    (N = 10^5); `which` selects among them."""
     ex = {}
+    if "mex" in which:
+        mex_extra(torch, np, etics, workloads, stream, reps, ex)
+    if "batched" in which:
+        batched_extra(torch, np, etics, workloads, stream, lf_steps, ex)
+    if "hermite" in which:
+        hermite_extra(torch, np, etics, workloads, stream, ex)
+    if "potonly" in which:
+        potonly_extra(torch, np, etics, workloads, stream, reps, ex)
+    if "cb" in which:
+        cb_extra(torch, np, etics, workloads, stream, reps, ex)
+    if "direct" in which:
+        direct_extra(torch, np, etics, workloads, stream, ex)
+    return ex
+
+
+def mex_extra(torch, np, etics, workloads, stream, reps, ex):
     p = workloads.make_config(4)
     n = p.x.shape[0]
     x, y, z, m = (torch.from_numpy(a).cuda() for a in (p.x, p.y, p.z, p.m))
@@ -341,15 +387,29 @@ def extras(torch, np, etics, workloads, stream, reps=10):
                              "algorithmic_bytes": mex_bytes,
                              "achieved_GBs": mex_bytes / (ms * 1e-3) / 1e9,
                              "frac_of_hbm_peak": mex_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
-    del x, y, z, m
+
+
+def batched_extra(torch, np, etics, workloads, stream, nsteps, ex):
     q = workloads.make_config(5)
     nt = q.x.shape[0]
     st = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (q.x, q.y, q.z, q.vx, q.vy, q.vz, q.m)]
+    ics = [t.clone() for t in st[:6]]
     off = torch.from_numpy(q.offsets).cuda()
     prec = etics.ETICS_MIXED_FP64ACC
     ws = etics.workspace(etics.etics_batched_workspace_size(nt, 256, 8, 6, prec), "cuda")
+
+    def energies():
+        """Per-system energy, kinetic plus half the mass-weighted SCF potential (FP64 on the GPU)."""
+        A, B = etics.etics_scf_coeffs_batched(*st[:3], st[6], off, 8, 6, etics.ETICS_FP64)
+        pot = etics.etics_scf_force_batched(*st[:3], off, 8, 6, A, B, etics.ETICS_FP64, etics.ETICS_POT)[0]
+        v2 = st[3] * st[3] + st[4] * st[4] + st[5] * st[5]
+        e = (0.5 * st[6] * (v2 + pot)).cpu().numpy()
+        return np.add.reduceat(e, q.offsets[:-1])
+
+    e_start = energies()
     etics.etics_leapfrog_scf_batched(*st, off, 8, 6, 0.01, 2, prec, 0, ws, stream)  # capture + warm
-    nsteps = 100
+    for t, t0 in zip(st[:6], ics):  # back to the initial conditions (same buffers: the graph stays valid)
+        t.copy_(t0)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
@@ -357,14 +417,96 @@ def extras(torch, np, etics, workloads, stream, reps=10):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    drift = np.abs(energies() / e_start - 1.0)
     # one call = one extra force calculation at the start + nsteps graph replays
     fc, ff = flops_per_particle(8, 6)
     step_ms = ms / (nsteps + 1)
     ex["leapfrog_batched_mixed"] = {"workload": "batched_256_spheres_n8_l6", "particles": nt, "nsteps": nsteps,
                                     "ms_per_call": ms, "ms_per_step": step_ms,
                                     "particle_steps_per_s": nt * (nsteps + 1) / (ms * 1e-3),
-                                    "step_tflops": (fc + ff) * nt / (step_ms * 1e-3) / 1e12}
-    del st, off, ws
+                                    "step_tflops": (fc + ff) * nt / (step_ms * 1e-3) / 1e12,
+                                    "plan": etics.etics_plan_info(nt, 8, 6, prec, batched=True),
+                                    "energy_drift_rel": {"median": float(np.median(drift)),
+                                                         "max": float(np.max(drift)),
+                                                         "what": f"|E(t)/E(0) - 1| per system after the "
+                                                                 f"{nsteps} mixed-precision steps of 0.01, E = "
+                                                                 f"kinetic + half the mass-weighted SCF potential"}}
+    del st, ics, off, ws
+
+
+def hermite_extra(torch, np, etics, workloads, stream, ex, nsteps=20):
+    """The batched fourth-order Hermite integrator on the 256-system workload (mixed):
+    a step is the coefficients and their time derivatives at the predicted state, the
+    jerk pass and the corrector, replayed from a captured graph."""
+    q = workloads.make_config(5)
+    nt = q.x.shape[0]
+    st = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (q.x, q.y, q.z, q.vx, q.vy, q.vz, q.m)]
+    ics = [t.clone() for t in st[:6]]
+    off = torch.from_numpy(q.offsets).cuda()
+    prec = etics.ETICS_MIXED_FP64ACC
+    ws = etics.workspace(etics.etics_hermite_workspace_size(nt, 256, 8, 6, prec), "cuda")
+
+    def energies():
+        A, B = etics.etics_scf_coeffs_batched(*st[:3], st[6], off, 8, 6, etics.ETICS_FP64)
+        pot = etics.etics_scf_force_batched(*st[:3], off, 8, 6, A, B, etics.ETICS_FP64, etics.ETICS_POT)[0]
+        v2 = st[3] * st[3] + st[4] * st[4] + st[5] * st[5]
+        return np.add.reduceat((0.5 * st[6] * (v2 + pot)).cpu().numpy(), q.offsets[:-1])
+
+    e_start = energies()
+    etics.etics_hermite_scf_batched(*st, off, 8, 6, 0.01, 2, prec, 0, ws, stream)  # capture + warm
+    for t, t0 in zip(st[:6], ics):
+        t.copy_(t0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    etics.etics_hermite_scf_batched(*st, off, 8, 6, 0.01, nsteps, prec, 0, ws, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    drift = np.abs(energies() / e_start - 1.0)
+    step_ms = ms / (nsteps + 1)  # one extra evaluation at the start
+    ex["hermite_batched_mixed"] = {"workload": "batched_256_spheres_n8_l6", "particles": nt, "nsteps": nsteps,
+                                   "ms_per_call": ms, "ms_per_step": step_ms,
+                                   "particle_steps_per_s": nt * (nsteps + 1) / (ms * 1e-3),
+                                   "energy_drift_rel": {"median": float(np.median(drift)),
+                                                        "max": float(np.max(drift)),
+                                                        "what": f"|E(t)/E(0) - 1| per system after {nsteps} "
+                                                                f"mixed-precision Hermite steps of 0.01"}}
+    del st, ics, off, ws
+
+
+def cb_extra(torch, np, etics, workloads, stream, reps, ex):
+    """One SCF force calculation in the Clutton-Brock basis (Section 2.5) at the headline
+    size and cutoffs, on a triaxial Plummer model (mixed)."""
+    p = workloads.triaxial_plummer(1_000_000, 2)
+    n = p.n
+    x, y, z, m = (torch.from_numpy(a).cuda() for a in (p.x, p.y, p.z, p.m))
+    prec, cb = etics.ETICS_MIXED_FP64ACC, etics.ETICS_BASIS_CB
+    K = etics.etics_coeff_count(10, 10)
+    A = torch.empty(K, dtype=torch.float64, device="cuda")
+    B = torch.empty_like(A)
+    outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    ws = etics.workspace(etics.etics_scf_workspace_size(n, 10, 10, prec), "cuda")
+
+    def step():
+        etics.etics_scf_coeffs_basis(x, y, z, m, 10, 10, prec, cb, A, B, ws, stream)
+        etics.etics_scf_force_basis(x, y, z, 10, 10, A, B, prec, cb, etics.ETICS_POT_ACC, *outs, ws, stream)
+
+    step()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ex["scf_clutton_brock_mixed"] = {"workload": "scf_triaxial_plummer_n1e6_n10_l10_cb", "ms_per_step": ms,
+                                     "particles_per_s": n / (ms * 1e-3)}
+    del x, y, z, m, A, B, outs, ws
+
+
+def potonly_extra(torch, np, etics, workloads, stream, reps, ex):
     # potential only (no acceleration): the SCF step of the headline workload with the
     # force call asked for ETICS_POT, which runs the kernel without the derivative sums
     p2 = workloads.make_config(2)
@@ -397,6 +539,9 @@ def extras(torch, np, etics, workloads, stream, reps=10):
     ex["scf_potential_only_mixed"] = {"workload": "scf_triaxial_hernquist_n1e6_n10_l10", "ms_per_step": ms,
                                       "particles_per_s": n2 / (ms * 1e-3), "force_kernel_ms": kt.mean_ms()}
     del x, y, z, m, A, B, pot, ws
+
+
+def direct_extra(torch, np, etics, workloads, stream, ex):
     # FP64 direct summation (the N-body reference of the accuracy study), N = 10^5
     # Ferrers model2: 19 flops per pair (3 differences, 5 for r^2, 1 reciprocal square
     # root, 3 for m/r and m/r^3, 1 for the potential, 6 for the acceleration)
@@ -420,7 +565,6 @@ def extras(torch, np, etics, workloads, stream, reps=10):
     ex["direct_fp64"] = {"workload": "direct_ferrers_model2_n1e5", "ms_per_call": ms,
                          "pairs_per_s": pairs / (ms * 1e-3), "flops_per_pair": 19,
                          "achieved_tflops": tf, "frac_of_fp64_peak": tf / PEAK_FP64_VECTOR_TFLOPS}
-    return ex
 
 
 if __name__ == "__main__":

@@ -269,12 +269,12 @@ int etics_set_timing_events(void* before, void* after);
    paper).  A coefficient call takes its tile shape from a plan: nw (wavefronts that
    share the basis work of a group of 64 particles: 4, 2 or 1, so a tile holds up to 64,
    128 or 256 particles), tp (particles per tile), streams (copies of the register
-   blocks merged at the end), grid_mult (workgroups per CU, 1 or 2) and, for
-   batched systems, unit (particles per work unit) and split (force workgroups per
-   unit).  Fixed rules give a plan for every cutoff; plans measured faster by the
-   project's tuner (paper_1406_4254_amd/tune.py) are kept in a table keyed by
-   (batched, nmax, lmax, precision, basis) and the particle count tuned at, and used
-   for calls within a factor of 8 of that count.  Every tuned value is checked against
+   blocks merged at the end), grid_mult (workgroups per CU, 1 or 2), phase2 (where the
+   FP32 outer products run: 1 = vector ALUs, 2 = matrix cores) and, for batched systems,
+   unit (particles per work unit) and split (force workgroups per unit).  Fixed rules
+   give a plan for every cutoff; plans measured faster by the project's tuner
+   (paper_1406_4254_amd/tune.py) are kept in a table keyed by (batched, nmax, lmax,
+   precision, basis) and the particle count tuned at, and used for calls within a factor of 8 of that count.  Every tuned value is checked against
    the kernel's limits; an invalid one falls back to the fixed rules.  The table is
    read on first use from $ETICS_TUNING_FILE, else from etics_tuning.json next to
    libetics.so (if present).  Workspace sizes follow the plan in force when they are
@@ -283,13 +283,13 @@ int etics_set_timing_events(void* before, void* after);
 
 /* Replace the table with the plans of a JSON file ({"plans": [{"batched": 0, "nmax": ..,
    "lmax": .., "prec": .., "basis": .., "n": .., "nw": .., "tp": .., "streams": ..,
-   "grid_mult": .., "unit": .., "split": ..}, ...]}; a missing or 0 parameter keeps the
-   fixed rule's value).  Returns the number of plans read, or ETICS_EINVAL if the file
+   "grid_mult": .., "unit": .., "split": .., "phase2": ..}, ...]}; a missing or 0
+   parameter keeps the fixed rule's value).  Returns the number of plans read, or ETICS_EINVAL if the file
    cannot be read or parsed (the table is then unchanged). */
 int etics_tuning_load(const char* path);
 
-/* Add or replace one plan; params = {nw, tp, streams, grid_mult, unit, split}
-   (nparams = 6; 0 keeps the fixed rule's value). */
+/* Add or replace one plan; params = {nw, tp, streams, grid_mult, unit, split, phase2}
+   (nparams = 7; 0 keeps the fixed rule's value). */
 int etics_tuning_set(int batched, int nmax, int lmax, int precision, int basis, int64_t n,
                      const int* params, int nparams);
 
@@ -297,8 +297,8 @@ int etics_tuning_set(int batched, int nmax, int lmax, int precision, int basis, 
 int etics_tuning_clear(void);
 
 /* The plan a coefficient call over n particles would use (batched: n = ntotal, basis
-   ETICS_BASIS_HO): out[0..7] = {nw, tp, streams, grid_mult, unit, split, tuned (0/1),
-   workgroups of a single-system launch}.  nout >= 8. */
+   ETICS_BASIS_HO): out[0..8] = {nw, tp, streams, grid_mult, unit, split, phase2, tuned
+   (0/1), workgroups of a single-system launch}.  nout >= 9. */
 int etics_plan_info(int batched, int64_t n, int nmax, int lmax, int precision, int basis, int* out,
                     int nout);
 

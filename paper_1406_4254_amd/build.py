@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libetics.so")
 
-SOURCES = ["etics_coeff.hip", "etics_coeff_dot.hip", "etics_force.hip", "etics_jerk.hip", "etics_mex.hip",
+SOURCES = ["etics_coeff.hip", "etics_coeff_dot.hip", "etics_coeff_mm.hip", "etics_coeff_mm_dot.hip",
+           "etics_force.hip", "etics_jerk.hip", "etics_mex.hip",
            "etics_batched.hip", "etics_direct.hip", "etics_abi.cpp", "etics_tune.cpp"]
 ARCH = os.environ.get("ETICS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -91,14 +91,15 @@ int etics_plan_info(int batched, int64_t n, int nmax, int lmax, int precision, i
   if (n < 0 || !valid_cut(nmax, lmax) || !valid_prec(precision)) return einval("n, cutoffs or precision");
   if (basis != ETICS_BASIS_HO && basis != ETICS_BASIS_CB) return einval("basis");
   if ((batched != 0 && batched != 1) || (batched && basis != ETICS_BASIS_HO)) return einval("batched");
-  if (!out || nout < 8) return einval("out needs 8 entries");
+  if (!out || nout < 9) return einval("out needs 9 entries");
   CoeffPlan p;
   if (!make_coeff_plan(n, nmax, lmax, precision, &p, basis, batched != 0)) {
     set_error("no tile plan for these cutoffs");
     return ETICS_EUNSUPPORTED;
   }
-  const int v[8] = {p.nw, p.tp, p.streams, p.grid_mult, p.unit, p.split, p.tuned ? 1 : 0, p.grid};
-  for (int i = 0; i < 8; ++i) out[i] = v[i];
+  const int v[9] = {p.nw, p.tp, p.streams, p.grid_mult, p.unit, p.split, p.mfma ? 2 : 1, p.tuned ? 1 : 0,
+                    p.grid};
+  for (int i = 0; i < 9; ++i) out[i] = v[i];
   return ETICS_OK;
 }
 

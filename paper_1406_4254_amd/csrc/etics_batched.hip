@@ -140,7 +140,7 @@ struct LeapfrogCall {
   void* ws;
   size_t ws_bytes;
   int device;
-  int plan[6];  // tile shape of the plan the step was captured with
+  int plan[7];  // tile shape of the plan the step was captured with
 };
 
 bool same_call(const LeapfrogCall& a, const LeapfrogCall& b) {
@@ -251,7 +251,7 @@ int run_leapfrog(double* x, double* y, double* z, double* vx, double* vy, double
     return ETICS_EWORKSPACE;
   }
   const CoeffPlan& plan = L.plan;
-  const int shape[6] = {plan.nw, plan.tp, plan.streams, plan.grid_mult, plan.unit, plan.split};
+  const int shape[7] = {plan.nw, plan.tp, plan.streams, plan.grid_mult, plan.unit, plan.split, plan.mfma ? 2 : 1};
   std::memcpy(c.plan, shape, sizeof shape);
   const Parts p = parts_of(c, L);
   rc = launch_units(offsets, nsys, ntotal, plan.unit, p.ustart, p.usys, st);

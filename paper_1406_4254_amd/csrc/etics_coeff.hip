@@ -139,23 +139,27 @@ size_t plan_per_particle(const CoeffPlan& q) {
   return size_t(q.spg + q.spz) * (q.prec == ETICS_FP64 ? 8 : 4);
 }
 
-// Complete a plan from its tile shape (nw particle groups, tp particles, streams); false
-// if the shape breaks a limit of the kernel: phase 1 has one lane per particle in each
-// of 4/nw groups of 64, phase 2 needs streams x nblocks lanes, and the tile and the
-// stream merge must fit the LDS.
-bool finish_plan(CoeffPlan& q, int nw, int tp, int streams) {
+// Complete a plan from its tile shape (nw particle groups, tp particles, streams, outer
+// products on the matrix cores or not); false if the shape breaks a limit of the
+// kernel: phase 1 has one lane per particle in each of 4/nw groups of 64; the VALU
+// phase 2 needs streams x nblocks lanes and an LDS stream merge, the matrix phase 2 an
+// FP32 mode; everything must fit the LDS.
+bool finish_plan(CoeffPlan& q, int nw, int tp, int streams, bool mfma) {
   if (!(nw == 4 || ((nw == 1 || nw == 2) && q.lb <= 6))) return false;
   if (streams < 1 || streams > kMaxStreams || streams * q.nblocks > kCoeffThreads) return false;
   if (tp < 1 || tp > 64 * (4 / nw)) return false;
+  if (mfma && q.prec == ETICS_FP64) return false;
   const size_t lds = size_t(tp) * plan_per_particle(q);
-  const size_t merge_bytes = size_t(q.nblocks) * q.nb * q.bs * 8;
+  const size_t merge_bytes = mfma ? 0 : size_t(q.nblocks) * q.nb * q.bs * 8;
   q.nw = nw;
   q.tp = tp;
   q.streams = streams;
+  q.mfma = mfma;
   q.lds_bytes = lds > merge_bytes ? lds : merge_bytes;
   if (q.lds_bytes > 160 * 1024) return false;
-  // FP32 runs of about 72 particles per lane before each fold
-  const int per_tile = q.tp / q.streams > 0 ? q.tp / q.streams : 1;
+  // FP32 runs of about 72 particles per lane (VALU) or per output entry (matrix cores)
+  // before each fold
+  const int per_tile = mfma ? q.tp : (q.tp / q.streams > 0 ? q.tp / q.streams : 1);
   q.flush_tiles = 72 / per_tile > 0 ? 72 / per_tile : 1;
   return true;
 }
@@ -209,8 +213,13 @@ bool make_coeff_plan(int64_t n, int nmax, int lmax, int prec, CoeffPlan* p, int 
     }
   }
   if (size_t(tp) * per_particle > budget) tp = int(budget / per_particle);
+  // Phase 2 on the VALU: the matrix-core variant needs two 32-bit LDS reads per lane per
+  // 256 products (and more for the ragged edges), so on this kernel it is bound by LDS
+  // traffic and latency rather than by the matrix cores, and measured slower at the
+  // larger cutoffs; the tuner takes it where it wins.
+  const bool mfma = false;
   if (streams <= tp) tp = tp / streams * streams;
-  if (!finish_plan(q, nw, tp, streams)) return false;
+  if (!finish_plan(q, nw, tp, streams, mfma)) return false;
   q.grid_mult = (esz == 4 && q.lds_bytes <= 80 * 1024) ? 2 : 1;
   q.unit = kUnitParticles;
   q.split = kForceSplit;
@@ -220,7 +229,8 @@ bool make_coeff_plan(int64_t n, int nmax, int lmax, int prec, CoeffPlan* p, int 
   if (tuned_lookup(batched ? 1 : 0, nmax, lmax, prec, basis, n, &t)) {
     CoeffPlan r = q;
     bool ok = finish_plan(r, t.nw > 0 ? t.nw : q.nw, t.tp > 0 ? t.tp : q.tp,
-                          t.streams > 0 ? t.streams : q.streams);
+                          t.streams > 0 ? t.streams : q.streams,
+                          t.phase2 > 0 ? t.phase2 == 2 : q.mfma);
     if (t.grid_mult > 0) r.grid_mult = t.grid_mult;
     if (t.unit > 0) r.unit = t.unit;
     if (t.split > 0) r.split = t.split;
@@ -294,9 +304,10 @@ int launch_scf_coeffs(const CoeffPlan& p, const double* x, const double* y, cons
 
 bool dot_plan(const CoeffPlan& p, int64_t n, CoeffPlan* out) {
   CoeffPlan q = p;
+  // two rows per particle: an even number of rows
   int tp = p.tp / 2 * 2;
-  if (tp < p.streams) tp = (p.streams + 1) / 2 * 2;
-  if (!finish_plan(q, p.nw, tp, p.streams)) return false;
+  if (!p.mfma && tp < p.streams) tp = (p.streams + 1) / 2 * 2;
+  if (!finish_plan(q, p.nw, tp, p.streams, p.mfma)) return false;
   q.grid = coeff_grid(q, (n + q.tp / 2 - 1) / (q.tp / 2));
   *out = q;
   return true;

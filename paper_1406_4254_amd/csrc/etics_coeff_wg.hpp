@@ -543,13 +543,168 @@ struct CoeffWG {
   }
 };
 
+// ------------------------------------------------------------ phase 2 on the matrix cores
+// In the FP32 modes phase 2 can run on the matrix cores instead of the VALU.  The sums of
+// one l form an (orders x slots) matrix of outer products summed over the particles; it
+// is cut into 4 x 4 blocks (4 orders x 4 angular slots), and v_mfma_f32_4x4x1f32
+// accumulates 16 such blocks at once, one particle per instruction: lanes 4b .. 4b+3
+// hold the four orders (A operand, from the radial row) and the four slots (B operand,
+// from the angular row) of block b, and accumulator register v of lane 4b + j holds
+// (order v, slot j) of block b.  4 x 4 blocks waste few entries on the ragged edges of
+// the (orders x (2l+1) slots) matrices (about a quarter at (10, 10)); larger tiles would
+// waste most of each instruction on the small l.  The blocks of the cutoff, slot blocks
+// fastest, are dealt 16 to an instruction and the instructions to the four wavefronts
+// round-robin, so the blocks of one instruction mostly share their radial values (one
+// LDS broadcast) and read consecutive angular slots.  The VALU is then left to phase 1
+// of the other wavefronts of the CU.
+template <int LB, int NRP>
+constexpr int mfma_block_count() {
+  int c = 0;
+  for (int l = 0; l <= LB; ++l) c += (NRP / 4) * (slot_pad(l, 4) / 4);
+  return c;
+}
+
+// block q of the cutoff (lmax, nmax): its l, first order and first slot; false past the
+// last block
+__device__ __forceinline__ bool mfma_block(int q, int lmax, int nmax, int& l, int& n0, int& s0) {
+  const int nt = nmax / 4 + 1;  // order blocks holding an order <= nmax
+  for (int k = 0; k <= lmax; ++k) {
+    const int sb = slot_pad(k, 4) / 4;
+    if (q < nt * sb) {
+      l = k;
+      n0 = 4 * (q / sb);
+      s0 = 4 * (q % sb);
+      return true;
+    }
+    q -= nt * sb;
+  }
+  l = n0 = s0 = 0;
+  return false;
+}
+
+template <int LB, int NB, int MODE, int NW, int BASIS>
+struct CoeffWGMM : CoeffWG<float, LB, NB, 4, MODE, NW, BASIS> {
+  using Base = CoeffWG<float, LB, NB, 4, MODE, NW, BASIS>;
+  using PT = typename Base::PT;
+  static constexpr int NRP = Base::NRP, SPG = Base::SPG, SPZ = Base::SPZ;
+  static constexpr int NI = (mfma_block_count<LB, NRP>() + 15) / 16;  // instructions per particle
+  static constexpr int JPW = (NI + 3) / 4;                            // ... per wavefront
+  // two accumulator sets (even and odd particles), so consecutive instructions on one
+  // block do not wait for each other
+  f32x4 macc[2][JPW];
+  Wide<float, MODE> mwide[JPW][4];
+  int aoff[JPW], boff[JPW];  // this lane's A / B element within a particle's rows
+
+  __device__ __forceinline__ void init(unsigned char* lds, int tp_, int lmax_, int nmax_,
+                                       int nblocks_, int streams_, int nchunks_) {
+    Base::init(lds, tp_, lmax_, nmax_, nblocks_, streams_, nchunks_);
+    const int i = this->lane & 3;
+#pragma unroll
+    for (int c = 0; c < JPW; ++c) {
+      int l, n0, s0;
+      // unused blocks read the first values of a row: in bounds, never written out
+      if (!mfma_block(16 * (this->wave + 4 * c) + (this->lane >> 2), this->lmax, this->nmax, l, n0, s0))
+        l = n0 = s0 = 0;
+      aoff[c] = l * NRP + n0 + i;
+      boff[c] = zoff_rt<4>(l) + s0 + i;
+    }
+    clear_mm();
+    clear_wide();
+  }
+  __device__ __forceinline__ void clear_mm() {
+#pragma unroll
+    for (int c = 0; c < JPW; ++c) macc[0][c] = macc[1][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  __device__ __forceinline__ void clear_wide() {
+#pragma unroll
+    for (int c = 0; c < JPW; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mwide[c][v] = Wide<float, MODE>{};
+  }
+  __device__ __forceinline__ void zero_slots() { Base::zero_slots(); }
+  __device__ __forceinline__ void fold() {
+#pragma unroll
+    for (int c = 0; c < JPW; ++c) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        mwide[c][v].add(macc[0][c][v]);
+        mwide[c][v].add(macc[1][c][v]);
+      }
+      macc[0][c] = macc[1][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+  // one particle per instruction, two per trip: the operands of the next particle are
+  // read before the instructions of the current one (the look-ahead past the tile is
+  // clamped to its last particle: read, never used), so the loop has no branch
+  __device__ __forceinline__ void phase2() {
+    using LT = __attribute__((address_space(3))) const float;
+    LT* gs = (LT*)(this->G);
+    LT* zs = (LT*)(this->Z);
+    float a0[JPW], b0[JPW], a1[JPW], b1[JPW];
+    auto load = [&](int p, float (&a)[JPW], float (&b)[JPW]) {
+      const int gb = p * SPG, zb = p * SPZ;
+#pragma unroll
+      for (int c = 0; c < JPW; ++c) {
+        a[c] = gs[gb + aoff[c]];
+        b[c] = zs[zb + boff[c]];
+      }
+    };
+    auto mma = [&](int set, const float (&a)[JPW], const float (&b)[JPW]) {
+#pragma unroll
+      for (int c = 0; c < JPW; ++c)
+        macc[set][c] = __builtin_amdgcn_mfma_f32_4x4x1f32(a[c], b[c], macc[set][c], 0, 0, 0);
+    };
+    const int last = this->tp - 1;
+    int p = 0;
+    load(0, a0, b0);
+    for (; p < last; p += 2) {
+      load(p + 1, a1, b1);
+      mma(0, a0, b0);
+      load(p + 2 < last ? p + 2 : last, a0, b0);
+      mma(1, a1, b1);
+    }
+    if (p == last) mma(0, a0, b0);
+  }
+  // every (n, l, slot) entry belongs to one lane of one wavefront: written straight to
+  // the partial vector (part[0..K) cos, part[K..2K) sin)
+  __device__ __forceinline__ void merge_write(unsigned char*, PT* part, int K) {
+    const int L2 = (this->lmax + 1) * (this->lmax + 2) / 2;
+    const int j = this->lane & 3;
+#pragma unroll
+    for (int c = 0; c < JPW; ++c) {
+      int l, n0, s0;
+      if (!mfma_block(16 * (this->wave + 4 * c) + (this->lane >> 2), this->lmax, this->nmax, l, n0, s0))
+        continue;
+      const int slot = s0 + j;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int nn = n0 + v;
+        if (nn > this->nmax || slot > 2 * l) continue;
+        const int m = slot == 2 * l ? 0 : slot / 2 + 1;
+        const bool is_sin = slot < 2 * l && (slot & 1) == 1;
+        part[(is_sin ? K : 0) + nn * L2 + l * (l + 1) / 2 + m] = wide_value(mwide[c][v]);
+      }
+    }
+  }
+};
+
+template <bool MM, typename T, int LB, int NB, int BS, int MODE, int NW, int BASIS>
+struct CoeffWGSel {
+  using type = CoeffWG<T, LB, NB, BS, MODE, NW, BASIS>;
+};
+template <int LB, int NB, int BS, int MODE, int NW, int BASIS>
+struct CoeffWGSel<true, float, LB, NB, BS, MODE, NW, BASIS> {
+  using type = CoeffWGMM<LB, NB, MODE, NW, BASIS>;
+};
+
 // DUAL: the time derivatives of the sums along the particles' velocities; every
 // particle then fills two rows of the tile, so a tile holds tp/2 particles.
-template <typename T, int LB, int NB, int BS, int MODE, int NW, int BASIS, bool DUAL>
+template <typename T, int LB, int NB, int BS, int MODE, int NW, int BASIS, bool DUAL, bool MM>
 __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coeff_kernel(
     const CoeffArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  CoeffWG<T, LB, NB, BS, MODE, NW, BASIS> w;
+  using W = typename CoeffWGSel<MM, T, LB, NB, BS, MODE, NW, BASIS>::type;
+  W w;
   w.init(lds_raw, a.tp, a.lmax, a.nmax, a.nblocks, a.streams, a.nchunks);
   w.zero_slots();
   __syncthreads();
@@ -592,7 +747,7 @@ __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coe
     __syncthreads();
   }
   w.fold();
-  using PT = typename CoeffWG<T, LB, NB, BS, MODE, NW, BASIS>::PT;
+  using PT = typename W::PT;
   w.merge_write(lds_raw, reinterpret_cast<PT*>(a.partials) + size_t(blockIdx.x) * 2 * a.K, a.K);
 }
 
@@ -611,11 +766,11 @@ struct BatchedCoeffArgs {
   int nsys, K, nmax, lmax, tp, nblocks, streams, nchunks, flush_tiles, unit;
 };
 
-template <typename T, int LB, int NB, int BS, int MODE, int NW, bool DUAL>
+template <typename T, int LB, int NB, int BS, int MODE, int NW, bool DUAL, bool MM>
 __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coeff_batched_kernel(
     const BatchedCoeffArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  using W = CoeffWG<T, LB, NB, BS, MODE, NW, kBasisHO>;
+  using W = typename CoeffWGSel<MM, T, LB, NB, BS, MODE, NW, kBasisHO>::type;
   W w;
   w.init(lds_raw, a.tp, a.lmax, a.nmax, a.nblocks, a.streams, a.nchunks);
   const int tpr = DUAL ? a.tp / 2 : a.tp;  // particles per tile
@@ -660,16 +815,16 @@ __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coe
 // Dispatch from a plan to the kernel instantiation of its cutoff bucket, register
 // block, accumulation mode and particle groups.
 
-template <bool BATCHED, bool DUAL, int BASIS, typename T, int LB, int NB, int BS, int MODE, int NW,
-          typename Args>
+template <bool BATCHED, bool DUAL, bool MM, int BASIS, typename T, int LB, int NB, int BS, int MODE,
+          int NW, typename Args>
 int launch_coeff_t(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
   static_assert(!(BATCHED || DUAL) || BASIS == kBasisHO,
                 "batched systems and time derivatives use the Hernquist-Ostriker basis");
   const void* kfn;
   if constexpr (BATCHED)
-    kfn = reinterpret_cast<const void*>(scf_coeff_batched_kernel<T, LB, NB, BS, MODE, NW, DUAL>);
+    kfn = reinterpret_cast<const void*>(scf_coeff_batched_kernel<T, LB, NB, BS, MODE, NW, DUAL, MM>);
   else
-    kfn = reinterpret_cast<const void*>(scf_coeff_kernel<T, LB, NB, BS, MODE, NW, BASIS, DUAL>);
+    kfn = reinterpret_cast<const void*>(scf_coeff_kernel<T, LB, NB, BS, MODE, NW, BASIS, DUAL, MM>);
   // the kernel has no static LDS: the whole 160 KiB of a CU may be requested (once per
   // device and kernel)
   static std::atomic<uint64_t> attr_done{0};
@@ -684,62 +839,81 @@ int launch_coeff_t(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) 
   int rc = hook_before(st);
   if (rc) return rc;
   if constexpr (BATCHED)
-    hipLaunchKernelGGL((scf_coeff_batched_kernel<T, LB, NB, BS, MODE, NW, DUAL>), dim3(grid),
+    hipLaunchKernelGGL((scf_coeff_batched_kernel<T, LB, NB, BS, MODE, NW, DUAL, MM>), dim3(grid),
                        dim3(kCoeffThreads), p.lds_bytes, st, a);
   else
-    hipLaunchKernelGGL((scf_coeff_kernel<T, LB, NB, BS, MODE, NW, BASIS, DUAL>), dim3(grid),
+    hipLaunchKernelGGL((scf_coeff_kernel<T, LB, NB, BS, MODE, NW, BASIS, DUAL, MM>), dim3(grid),
                        dim3(kCoeffThreads), p.lds_bytes, st, a);
   rc = hip_fail(hipGetLastError(), "scf_coeff_kernel launch");
   return rc ? rc : hook_after(st);
 }
 
-template <bool BATCHED, bool DUAL, typename T, int MODE, int LB, int NW, int NB, typename Args>
+template <bool BATCHED, bool DUAL, bool MM, typename T, int MODE, int LB, int NW, int NB, typename Args>
 int launch_coeff_basis(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
   if constexpr (!BATCHED && !DUAL) {
     if (p.basis == kBasisCB)
-      return launch_coeff_t<BATCHED, DUAL, kBasisCB, T, LB, NB, 4, MODE, NW>(p, a, grid, st);
+      return launch_coeff_t<BATCHED, DUAL, MM, kBasisCB, T, LB, NB, 4, MODE, NW>(p, a, grid, st);
   }
-  return launch_coeff_t<BATCHED, DUAL, kBasisHO, T, LB, NB, 4, MODE, NW>(p, a, grid, st);
+  return launch_coeff_t<BATCHED, DUAL, MM, kBasisHO, T, LB, NB, 4, MODE, NW>(p, a, grid, st);
 }
 
-template <bool BATCHED, bool DUAL, typename T, int MODE, int LB, int NW, typename Args>
+template <bool BATCHED, bool DUAL, bool MM, typename T, int MODE, int LB, int NW, typename Args>
 int launch_coeff_nb(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
   switch (p.nb) {
-    case 9: return launch_coeff_basis<BATCHED, DUAL, T, MODE, LB, NW, 9>(p, a, grid, st);
-    case 11: return launch_coeff_basis<BATCHED, DUAL, T, MODE, LB, NW, 11>(p, a, grid, st);
-    default: return launch_coeff_basis<BATCHED, DUAL, T, MODE, LB, NW, 12>(p, a, grid, st);
+    case 9: return launch_coeff_basis<BATCHED, DUAL, MM, T, MODE, LB, NW, 9>(p, a, grid, st);
+    case 11: return launch_coeff_basis<BATCHED, DUAL, MM, T, MODE, LB, NW, 11>(p, a, grid, st);
+    default: return launch_coeff_basis<BATCHED, DUAL, MM, T, MODE, LB, NW, 12>(p, a, grid, st);
   }
 }
 
 // particle groups per tile: only the small cutoff buckets have the LDS for 128 or 256
 // particles per tile
-template <bool BATCHED, bool DUAL, typename T, int MODE, int LB, typename Args>
+template <bool BATCHED, bool DUAL, bool MM, typename T, int MODE, int LB, typename Args>
 int launch_coeff_nw(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
   if constexpr (LB <= 6) {
-    if (p.nw == 1) return launch_coeff_nb<BATCHED, DUAL, T, MODE, LB, 1>(p, a, grid, st);
-    if (p.nw == 2) return launch_coeff_nb<BATCHED, DUAL, T, MODE, LB, 2>(p, a, grid, st);
+    if (p.nw == 1) return launch_coeff_nb<BATCHED, DUAL, MM, T, MODE, LB, 1>(p, a, grid, st);
+    if (p.nw == 2) return launch_coeff_nb<BATCHED, DUAL, MM, T, MODE, LB, 2>(p, a, grid, st);
   }
-  return launch_coeff_nb<BATCHED, DUAL, T, MODE, LB, 4>(p, a, grid, st);
+  return launch_coeff_nb<BATCHED, DUAL, MM, T, MODE, LB, 4>(p, a, grid, st);
+}
+
+template <bool BATCHED, bool DUAL, bool MM, typename T, int MODE, typename Args>
+int launch_coeff_lb(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
+  switch (p.lb) {
+    case 2: return launch_coeff_nw<BATCHED, DUAL, MM, T, MODE, 2>(p, a, grid, st);
+    case 6: return launch_coeff_nw<BATCHED, DUAL, MM, T, MODE, 6>(p, a, grid, st);
+    case 10: return launch_coeff_nw<BATCHED, DUAL, MM, T, MODE, 10>(p, a, grid, st);
+    default: return launch_coeff_nw<BATCHED, DUAL, MM, T, MODE, 14>(p, a, grid, st);
+  }
+}
+
+// the matrix-core phase 2 (FP32 modes): instantiated in etics_coeff_mm.hip (sums) and
+// etics_coeff_mm_dot.hip (time derivatives), so their compile time is spread over files
+int launch_coeff_mm(const CoeffPlan& p, const CoeffArgs& a, int grid, hipStream_t st);
+int launch_coeff_mm(const CoeffPlan& p, const BatchedCoeffArgs& a, int grid, hipStream_t st);
+int launch_coeff_mm_dual(const CoeffPlan& p, const CoeffArgs& a, int grid, hipStream_t st);
+int launch_coeff_mm_dual(const CoeffPlan& p, const BatchedCoeffArgs& a, int grid, hipStream_t st);
+
+template <bool BATCHED, bool DUAL, bool MM, typename Args>
+int launch_coeff_modes(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
+  if constexpr (MM) {
+    if (p.prec == ETICS_FP64) {
+      set_error("internal: matrix-core phase 2 is FP32 only");
+      return ETICS_EUNSUPPORTED;
+    }
+    if (p.prec == ETICS_MIXED_FP64ACC) return launch_coeff_lb<BATCHED, DUAL, true, float, 0>(p, a, grid, st);
+    return launch_coeff_lb<BATCHED, DUAL, true, float, 1>(p, a, grid, st);
+  } else {
+    if (p.prec == ETICS_FP64) return launch_coeff_lb<BATCHED, DUAL, false, double, 0>(p, a, grid, st);
+    if (p.prec == ETICS_MIXED_FP64ACC) return launch_coeff_lb<BATCHED, DUAL, false, float, 0>(p, a, grid, st);
+    return launch_coeff_lb<BATCHED, DUAL, false, float, 1>(p, a, grid, st);
+  }
 }
 
 template <bool BATCHED, bool DUAL, typename Args>
 int launch_coeff_any(const CoeffPlan& p, const Args& a, int grid, hipStream_t st) {
-  const int mode = p.prec == ETICS_FP64 ? 0 : (p.prec == ETICS_MIXED_FP64ACC ? 1 : 2);
-#define ETICS_LB_CASES(T, MODE)                                                  \
-  switch (p.lb) {                                                                \
-    case 2: return launch_coeff_nw<BATCHED, DUAL, T, MODE, 2>(p, a, grid, st);   \
-    case 6: return launch_coeff_nw<BATCHED, DUAL, T, MODE, 6>(p, a, grid, st);   \
-    case 10: return launch_coeff_nw<BATCHED, DUAL, T, MODE, 10>(p, a, grid, st); \
-    default: return launch_coeff_nw<BATCHED, DUAL, T, MODE, 14>(p, a, grid, st); \
-  }
-  if (mode == 0) {
-    ETICS_LB_CASES(double, 0)
-  } else if (mode == 1) {
-    ETICS_LB_CASES(float, 0)
-  } else {
-    ETICS_LB_CASES(float, 1)
-  }
-#undef ETICS_LB_CASES
+  if (p.mfma) return DUAL ? launch_coeff_mm_dual(p, a, grid, st) : launch_coeff_mm(p, a, grid, st);
+  return launch_coeff_modes<BATCHED, DUAL, false>(p, a, grid, st);
 }
 
 // host side (etics_coeff.hip): argument blocks, the fixed-order reductions and the plan

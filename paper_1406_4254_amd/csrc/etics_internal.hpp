@@ -52,13 +52,15 @@ struct CoeffPlan {
   int grid_mult;          // workgroups per CU (grid = 256 grid_mult, at most the work items)
   int grid;               // workgroups of a single-system launch
   int unit, split;        // batched: particles per work unit, force workgroups per unit
+  bool mfma;              // FP32 outer products on the matrix cores (else the VALU)
   bool tuned;             // the tile shape came from the tuner's table
   size_t lds_bytes;
 };
 
-// Tile shape measured by the tuner (0 = keep the fixed rule's value).
+// Tile shape measured by the tuner (0 = keep the fixed rule's value; phase2: 1 = VALU,
+// 2 = matrix cores).
 struct TunedParams {
-  int nw, tp, streams, grid_mult, unit, split;
+  int nw, tp, streams, grid_mult, unit, split, phase2;
 };
 // The tuner's plan for this key and particle count, if it holds one (etics_tune.cpp).
 bool tuned_lookup(int batched, int nmax, int lmax, int prec, int basis, int64_t n, TunedParams* out);

@@ -298,7 +298,7 @@ struct HermiteCall {
   void* ws;
   size_t ws_bytes;
   int device;
-  int plan[6];
+  int plan[7];
 };
 
 bool same_call(const HermiteCall& a, const HermiteCall& b) {
@@ -417,7 +417,7 @@ int run_hermite(double* x, double* y, double* z, double* vx, double* vy, double*
     return ETICS_EWORKSPACE;
   }
   const CoeffPlan& plan = L.plan;
-  const int shape[6] = {plan.nw, plan.tp, plan.streams, plan.grid_mult, plan.unit, plan.split};
+  const int shape[7] = {plan.nw, plan.tp, plan.streams, plan.grid_mult, plan.unit, plan.split, plan.mfma ? 2 : 1};
   std::memcpy(c.plan, shape, sizeof shape);
   char* base = reinterpret_cast<char*>(ws);
   rc = launch_units(offsets, nsys, ntotal, plan.unit, reinterpret_cast<int*>(base + L.off_ustart),

@@ -1,8 +1,9 @@
 // etics_tune.cpp -- tile plans chosen by the autotuner.
 //
 // The coefficient kernels take their tile shape from a plan (particles per tile,
-// particle groups per tile, stream copies, workgroups per CU; for batched systems also
-// the particles per work unit and the force workgroups per unit).  make_coeff_plan
+// particle groups per tile, stream copies, workgroups per CU, outer products on the
+// vector ALUs or the matrix cores; for batched systems also the particles per work unit
+// and the force workgroups per unit).  make_coeff_plan
 // derives a plan from fixed rules; this table holds plans measured to be faster on
 // the device by the project's tuner (paper_1406_4254_amd/tune.py), keyed by
 // (batched, nmax, lmax, precision, basis) and the particle count they were tuned at.
@@ -157,7 +158,7 @@ int parse_plans(const std::string& text, std::vector<Entry>* out) {
   Reader r{text.data(), text.data() + text.size(), {}};
   if (!r.value(0, nullptr, "")) return -1;
   static const char* kKey[5] = {"batched", "nmax", "lmax", "prec", "basis"};
-  static const char* kPar[6] = {"nw", "tp", "streams", "grid_mult", "unit", "split"};
+  static const char* kPar[7] = {"nw", "tp", "streams", "grid_mult", "unit", "split", "phase2"};
   for (const auto& m : r.plans) {
     Entry en{};
     bool ok = true;
@@ -171,8 +172,8 @@ int parse_plans(const std::string& text, std::vector<Entry>* out) {
     auto itn = m.find("n");
     if (itn == m.end() || !(itn->second >= 1.0) || !(itn->second < 9.0e18)) ok = false;
     if (ok) en.n = int64_t(itn->second);
-    int* par[6] = {&en.t.nw, &en.t.tp, &en.t.streams, &en.t.grid_mult, &en.t.unit, &en.t.split};
-    for (int i = 0; i < 6 && ok; ++i) {
+    int* par[7] = {&en.t.nw, &en.t.tp, &en.t.streams, &en.t.grid_mult, &en.t.unit, &en.t.split, &en.t.phase2};
+    for (int i = 0; i < 7 && ok; ++i) {
       auto it = m.find(kPar[i]);
       const double v = it == m.end() ? 0.0 : it->second;  // 0 = keep the fixed rule
       if (!fits_int(v)) ok = false;
@@ -266,14 +267,14 @@ int etics_tuning_clear(void) {
 
 int etics_tuning_set(int batched, int nmax, int lmax, int precision, int basis, int64_t n,
                      const int* params, int nparams) {
-  if (!params || nparams != 6 || n < 1 || (batched != 0 && batched != 1)) {
-    set_error("etics_tuning_set: need 6 parameters, n >= 1 and batched 0 or 1");
+  if (!params || nparams != 7 || n < 1 || (batched != 0 && batched != 1)) {
+    set_error("etics_tuning_set: need 7 parameters, n >= 1 and batched 0 or 1");
     return ETICS_EINVAL;
   }
   std::lock_guard<std::mutex> lock(g_mu);
   ensure_loaded_locked();
   Entry en{{batched, nmax, lmax, precision, basis}, n,
-           {params[0], params[1], params[2], params[3], params[4], params[5]}};
+           {params[0], params[1], params[2], params[3], params[4], params[5], params[6]}};
   for (Entry& e : g_tab)
     if (std::memcmp(e.key, en.key, sizeof en.key) == 0 && e.n == n) {
       e = en;

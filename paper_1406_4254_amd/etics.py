@@ -212,7 +212,7 @@ def etics_set_timing_events(before, after) -> None:
     _check(lib().etics_set_timing_events(hb, ha))
 
 
-PLAN_FIELDS = ("nw", "tp", "streams", "grid_mult", "unit", "split")
+PLAN_FIELDS = ("nw", "tp", "streams", "grid_mult", "unit", "split", "phase2")
 
 
 def etics_tuning_load(path: str) -> int:
@@ -225,8 +225,8 @@ def etics_tuning_load(path: str) -> int:
 def etics_tuning_set(nmax: int, lmax: int, precision, n: int, plan: dict, batched=False,
                      basis=ETICS_BASIS_HO) -> None:
     """Add or replace one tuned plan (missing fields keep the fixed rules' values)."""
-    vals = (_int * 6)(*[int(plan.get(k, 0)) for k in PLAN_FIELDS])
-    _check(lib().etics_tuning_set(int(bool(batched)), nmax, lmax, _prec(precision), int(basis), int(n), vals, 6))
+    vals = (_int * 7)(*[int(plan.get(k, 0)) for k in PLAN_FIELDS])
+    _check(lib().etics_tuning_set(int(bool(batched)), nmax, lmax, _prec(precision), int(basis), int(n), vals, 7))
 
 
 def etics_tuning_clear() -> None:
@@ -235,11 +235,11 @@ def etics_tuning_clear() -> None:
 
 def etics_plan_info(n: int, nmax: int, lmax: int, precision, batched=False, basis=ETICS_BASIS_HO) -> dict:
     """The tile plan a coefficient call over n particles would use."""
-    out = (_int * 8)()
-    _check(lib().etics_plan_info(int(bool(batched)), int(n), nmax, lmax, _prec(precision), int(basis), out, 8))
-    d = dict(zip(PLAN_FIELDS, out[:6]))
-    d["tuned"] = bool(out[6])
-    d["grid"] = out[7]
+    out = (_int * 9)()
+    _check(lib().etics_plan_info(int(bool(batched)), int(n), nmax, lmax, _prec(precision), int(basis), out, 9))
+    d = dict(zip(PLAN_FIELDS, out[:7]))
+    d["tuned"] = bool(out[7])
+    d["grid"] = out[8]
     return d
 
 

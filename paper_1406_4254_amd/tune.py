@@ -3,7 +3,8 @@
 The coefficient kernels (single system and batched) take their tile shape from a plan
 (see include/etics.h, "Tile plans and the autotuner"): wavefronts per particle group
 ``nw``, particles per tile ``tp``, stream copies ``streams``, workgroups per CU
-``grid_mult`` and, for batched systems, particles per work unit ``unit`` and force
+``grid_mult``, where the FP32 outer products run ``phase2`` (1 = vector ALUs, 2 =
+matrix cores) and, for batched systems, particles per work unit ``unit`` and force
 workgroups per unit ``split``.  The library derives a plan from fixed rules; this
 module measures candidate plans on the device and keeps the fastest per workload:
 
@@ -57,17 +58,25 @@ def _rel(A, B, A0, B0):
     return float(torch.linalg.norm(d) / torch.linalg.norm(r))
 
 
-def single_candidates(base, lmax):
+def single_candidates(base, lmax, prec):
     """Shapes around the fixed plan of a single-system coefficient call (1 or 2
-    wavefronts per particle group exist for lmax <= 6 only)."""
-    smax = base["streams"]
+    wavefronts per particle group exist for lmax <= 6 only; the matrix-core phase 2 for
+    the FP32 modes only, without streams)."""
+    smax = max(base["streams"], 1)
     nws = [1, 2, 4] if lmax <= 6 else [4]
     out = []
     for nw, s, gm in itertools.product(nws, range(1, smax + 1), (1, 2)):
         tmax = 64 * (4 // nw)
         tps = sorted({t for t in (tmax // s * s, (3 * tmax // 4) // s * s, (tmax // 2) // s * s) if t >= s})
         for tp in tps:
-            out.append({"nw": nw, "tp": tp, "streams": s, "grid_mult": gm, "unit": 0, "split": 0})
+            out.append({"nw": nw, "tp": tp, "streams": s, "grid_mult": gm, "unit": 0, "split": 0, "phase2": 1})
+    if prec != E.ETICS_FP64:
+        for nw, gm in itertools.product(nws, (1, 2)):
+            tmax = 64 * (4 // nw)
+            for tp in sorted({tmax, 3 * tmax // 4 // 4 * 4, tmax // 2, 60, 56, 48, 32}):
+                if 4 <= tp <= tmax:
+                    out.append({"nw": nw, "tp": tp, "streams": base["streams"], "grid_mult": gm, "unit": 0,
+                                "split": 0, "phase2": 2})
     return out
 
 
@@ -78,14 +87,14 @@ def batched_candidates(base):
         if unit // split < 64:
             continue
         out.append({"nw": base["nw"], "tp": base["tp"], "streams": base["streams"], "grid_mult": gm,
-                    "unit": unit, "split": split})
-    for nw in (1, 2, 4):
+                    "unit": unit, "split": split, "phase2": base["phase2"]})
+    for nw, ph in itertools.product((1, 2, 4), (1, 2)):
         tmax = 64 * (4 // nw)
         s = base["streams"]
         if s > tmax:
             continue
-        out.append({"nw": nw, "tp": tmax // s * s, "streams": s, "grid_mult": base["grid_mult"],
-                    "unit": base["unit"], "split": base["split"]})
+        out.append({"nw": nw, "tp": tmax // s * s if ph == 1 else tmax, "streams": s,
+                    "grid_mult": base["grid_mult"], "unit": base["unit"], "split": base["split"], "phase2": ph})
     return out
 
 
@@ -118,7 +127,7 @@ def tune_single(name, p, nmax, lmax, prec, basis=E.ETICS_BASIS_HO, reps=7, margi
     base, base_ms, A0, B0 = run_plan(None)
     tol = 1e-12 if prec == E.ETICS_FP64 else 2e-5
     rows = [dict(_shape(base), ms=base_ms, rel=0.0, fixed=True)]
-    for c in single_candidates(base, lmax):
+    for c in single_candidates(base, lmax, prec):
         info, ms, A1, B1 = run_plan(c)
         E.etics_tuning_clear()
         if not _in_force(info, c):
@@ -258,7 +267,7 @@ def main(argv=None):
     print(f"wrote {len(plans)} plans to {args.out}")
 
 
-def report(doc, tables, cmd, secs):
+def report(doc, tables, cmd, secs, shown=8):
     lines = [f"# Coefficient-kernel tile plans measured by the autotuner ({doc['device']})", "",
              "Command (R = repository root; the tuner times each candidate plan with HIP events, "
              "median of repeated coefficient calls, batched: coefficients + force):", "", "```",
@@ -266,19 +275,28 @@ def report(doc, tables, cmd, secs):
              f"{sum(len(t[2]) for t in tables)} plans measured in {secs:.0f} s; the three fastest "
              f"candidates and the fixed rules' plan are then timed again in 5 interleaved rounds, and a "
              f"candidate replaces the fixed plan only if its median is at least "
-             f"{100 * doc['margin']:.0f}% faster.", ""]
+             f"{100 * doc['margin']:.0f}% faster.  The library reads the written table from "
+             f"etics_tuning.json next to libetics.so (or $ETICS_TUNING_FILE).", ""]
     lines += ["| workload | fixed plan ms | chosen ms | speed-up | chosen plan |", "|---|---|---|---|---|"]
     for tag, plan, rows in tables:
         lines.append(f"| {tag} | {plan['fixed_ms']:.4f} | {plan['ms']:.4f} | "
                      f"{plan['fixed_ms'] / plan['ms']:.3f} | {plan['source']}: "
                      f"{ {k: plan[k] for k in E.PLAN_FIELDS} } |")
     for tag, plan, rows in tables:
-        lines += ["", f"## {tag}", "", "| nw | tp | streams | grid_mult | unit | split | ms | rel. diff vs fixed |",
-                  "|---|---|---|---|---|---|---|---|"]
-        for r in sorted(rows, key=lambda r: r["ms"]):
+        order = sorted(rows, key=lambda r: r["ms"])
+        # the fastest few, the fixed plan and the fastest of each phase-2 kind
+        keep = order[:shown]
+        for r in order:
+            if r not in keep and (r["fixed"] or all(k["phase2"] != r["phase2"] for k in keep)):
+                keep.append(r)
+        lines += ["", f"## {tag}", "", f"{len(keep)} of {len(rows)} candidates, fastest first.", "",
+                  "| phase2 | nw | tp | streams | grid_mult | unit | split | ms | rel. diff vs fixed |",
+                  "|---|---|---|---|---|---|---|---|---|"]
+        for r in sorted(keep, key=lambda r: r["ms"]):
             mark = " (fixed rules)" if r["fixed"] else ""
             mark += " (re-timed: median of 5 interleaved rounds)" if r.get("retimed") else ""
-            lines.append(f"| {r['nw']} | {r['tp']} | {r['streams']} | {r['grid_mult']} | {r['unit']} | "
+            ph = "matrix" if r["phase2"] == 2 else "VALU"
+            lines.append(f"| {ph} | {r['nw']} | {r['tp']} | {r['streams']} | {r['grid_mult']} | {r['unit']} | "
                          f"{r['split']} | {r['ms']:.4f}{mark} | {r['rel']:.1e} |")
     return "\n".join(lines) + "\n"
 
