@@ -13,10 +13,10 @@
 // Steps (all on the caller's stream):
 //   1. mex_keys: FP64 key (x*x + y*y) + z*z, each operation rounded, as its IEEE bit
 //      pattern (order-preserving for non-negative values), with the particle index.
-//   2. LSD radix sort of (key, index), 8 bits per pass: per-block digit histograms,
-//      a per-digit exclusive scan over blocks (one workgroup per digit), a stable
-//      scatter whose in-block ranks come from wavefront ballots.  Stable, so equal keys
-//      stay in index order.
+//   2. LSD radix sort of (key, index), 8 bits per pass, three kernels per pass: the
+//      digit counts of every tile of keys, a scan of each digit's counts over the tiles,
+//      then every tile ranks its keys stably in LDS and writes them as runs of equal
+//      digit.  Stable, so equal keys stay in index order.
 //   3. mex_tile_sums: per tile of sorted particles, the sums of the inward and outward
 //      summands (FP64); each 16-lane row of a wavefront sums one LDS column, a lane
 //      adding 8 consecutive rows before a row tree.
@@ -46,8 +46,10 @@ constexpr int kMexTile = 128;       // sorted particles per tile (one per thread
 constexpr int kMexColStride = kMexTile + 2 * (kMexTile / 16);  // 144 doubles
 __device__ __forceinline__ int mex_row_pos(int t) { return t + 2 * (t >> 4); }
 constexpr int kMexBlockTiles = 16;  // tiles per block of the tile-offset scan
-constexpr int kSortSeg = 4096;      // keys per radix block
 constexpr int kSortThreads = 256;
+constexpr int kSortKPT = 8;                         // keys per thread of a radix pass
+constexpr int kSortTile = kSortThreads * kSortKPT;  // keys per tile of a radix pass
+constexpr int kSortPasses = 8;                      // 8-bit digits of a 64-bit key
 
 // ------------------------------------------------------------------ block scans
 // exclusive prefix sum of one value per thread over a workgroup of 256 threads
@@ -92,35 +94,62 @@ __global__ __launch_bounds__(256) void mex_keys_kernel(const double* __restrict_
 }
 
 // ------------------------------------------------------------------ radix sort
-// hist[d * nblk + b] = number of keys of block b with digit d
-__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint64_t* __restrict__ key,
-                                                                  int64_t n, int shift, int nblk,
-                                                                  uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t b0 = int64_t(blockIdx.x) * kSortSeg;
-  const int64_t b1 = b0 + kSortSeg < n ? b0 + kSortSeg : n;
-  for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads)
-    atomicAdd(&h[(key[i] >> shift) & 0xff], 1u);
-  __syncthreads();
-  hist[size_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
+// The lanes of a wavefront whose digit equals this lane's (8 ballots; only valid lanes)
+__device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, bool valid) {
+  uint64_t same = __ballot(valid);
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    const uint64_t bb = __ballot((d >> bit) & 1u);
+    same &= ((d >> bit) & 1u) ? bb : ~bb;
+  }
+  return same;
 }
 
-// hist[d * nblk + b] -> exclusive prefix over blocks b of digit d (in place);
+// counts[d * ntiles + tile] = keys of the tile with digit d.  Lanes with equal digits
+// add their number once, so a digit shared by many keys (the exponent bytes) does not
+// serialize on one LDS word.
+__global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const uint64_t* __restrict__ key,
+                                                                   int64_t n, int shift, int ntiles,
+                                                                   uint32_t* __restrict__ counts) {
+  __shared__ uint32_t h[256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  h[t] = 0;
+  __syncthreads();
+  const int64_t t0 = int64_t(blockIdx.x) * kSortTile;
+  const int tn = int(n - t0 < kSortTile ? n - t0 : kSortTile);
+  constexpr int Q = kSortTile / 4;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  uint64_t k[kSortKPT];
+#pragma unroll
+  for (int j = 0; j < kSortKPT; ++j) {
+    const int i = w * Q + j * 64 + lane;
+    k[j] = i < tn ? key[t0 + i] : 0ull;
+  }
+#pragma unroll
+  for (int j = 0; j < kSortKPT; ++j) {
+    const bool valid = w * Q + j * 64 + lane < tn;
+    const uint32_t d = uint32_t(k[j] >> shift) & 0xffu;
+    const uint64_t same = same_digit_lanes(d, valid);
+    if (valid && (same & lt_mask) == 0) atomicAdd(&h[d], uint32_t(__popcll(same)));
+  }
+  __syncthreads();
+  counts[size_t(t) * ntiles + blockIdx.x] = h[t];
+}
+
+// counts[d * ntiles + b] -> exclusive prefix over tiles b of digit d (in place);
 // totals[d] = keys with digit d.  One workgroup per digit.
-__global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restrict__ hist, int nblk,
+__global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restrict__ counts, int ntiles,
                                                                uint32_t* __restrict__ totals) {
   __shared__ uint32_t wsum[4];
-  uint32_t* row = hist + size_t(blockIdx.x) * nblk;
+  uint32_t* row = counts + size_t(blockIdx.x) * ntiles;
   const int t = threadIdx.x;
   uint32_t carry = 0;
-  for (int base = 0; base < nblk; base += 4 * 256) {
+  for (int base = 0; base < ntiles; base += 4 * 256) {
     uint32_t v[4], s = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int i = base + 4 * t + j;
-      v[j] = i < nblk ? row[i] : 0u;
+      v[j] = i < ntiles ? row[i] : 0u;
       s += v[j];
     }
     uint32_t chunk;
@@ -128,7 +157,7 @@ __global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restr
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int i = base + 4 * t + j;
-      if (i < nblk) row[i] = run;
+      if (i < ntiles) row[i] = run;
       run += v[j];
     }
     carry += chunk;
@@ -136,52 +165,85 @@ __global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restr
   if (t == 0) totals[blockIdx.x] = carry;
 }
 
-// Stable scatter.  The block walks its segment in chunks of 256 keys (one per
-// thread, in order); a key's rank among equal digits is (keys of that digit in
-// earlier chunks) + (in earlier wavefronts of this chunk) + (in earlier lanes of its
-// wavefront, from 8 ballots).
+// Stable scatter of one tile: the keys are ranked in LDS (wavefront w ranks keys
+// [w Q, (w+1) Q) of the tile in order, 64 at a time: a key's rank among equal digits of
+// its wavefront's range is the running count of the digit plus the equal digits in lower
+// lanes; the lowest lane of each digit group advances the count; one wavefront reads and
+// writes its own row of counts, in program order, so no barrier is needed), placed in
+// digit order in LDS, and written out so that consecutive threads write consecutive
+// positions of each digit's run.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, int64_t n, int shift, int nblk, const uint32_t* __restrict__ hist,
+    uint32_t* __restrict__ vout, int64_t n, int shift, int ntiles, const uint32_t* __restrict__ counts,
     const uint32_t* __restrict__ totals) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[4][256];
+  __shared__ uint64_t sk[kSortTile];
+  __shared__ uint32_t sv[kSortTile];
+  __shared__ uint32_t cnt[4][256];  // per wavefront: running digit counts, then bases
+  __shared__ uint32_t gbase[256];
   __shared__ uint32_t wsum[4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  uint32_t all;
-  const uint32_t digit_start = block_excl_scan_u32(totals[t], wsum, &all);
-  base[t] = digit_start + hist[size_t(t) * nblk + blockIdx.x];
-  const int64_t b0 = int64_t(blockIdx.x) * kSortSeg;
-  const int64_t b1 = b0 + kSortSeg < n ? b0 + kSortSeg : n;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int64_t c0 = b0; c0 < b1; c0 += kSortThreads) {
-    for (int q = 0; q < 4; ++q) wcnt[q][t] = 0;
-    __syncthreads();
-    const int64_t i = c0 + t;
-    const bool valid = i < b1;
-    const uint64_t k = valid ? kin[i] : 0ull;
-    const uint32_t v = valid ? vin[i] : 0u;
-    const uint32_t d = uint32_t(k >> shift) & 0xffu;
-    uint64_t same = __ballot(valid);
+  for (int i = t; i < 4 * 256; i += kSortThreads) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+  const int tile = blockIdx.x;
+  const int64_t t0 = int64_t(tile) * kSortTile;
+  const int tn = int(n - t0 < kSortTile ? n - t0 : kSortTile);  // keys of this tile
+  constexpr int Q = kSortTile / 4;
+  uint64_t k[kSortKPT];
+  uint32_t v[kSortKPT], rank[kSortKPT];
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-      const uint64_t bb = __ballot((d >> bit) & 1u);
-      same &= ((d >> bit) & 1u) ? bb : ~bb;
-    }
+  for (int j = 0; j < kSortKPT; ++j) {
+    const int i = w * Q + j * 64 + lane;
+    k[j] = i < tn ? kin[t0 + i] : 0ull;
+    v[j] = i < tn ? vin[t0 + i] : 0u;
+  }
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int j = 0; j < kSortKPT; ++j) {
+    const bool valid = w * Q + j * 64 + lane < tn;
+    const uint32_t d = uint32_t(k[j] >> shift) & 0xffu;
+    const uint64_t same = same_digit_lanes(d, valid);
     const uint32_t below = uint32_t(__popcll(same & lt_mask));
-    const uint32_t cnt = uint32_t(__popcll(same));
-    // the lowest lane of each digit group publishes the wavefront's count
-    if (valid && below == 0) wcnt[w][d] = cnt;
-    __syncthreads();
+    uint32_t r = 0;
     if (valid) {
-      uint32_t r = base[d] + below;
-      for (int q = 0; q < w; ++q) r += wcnt[q][d];
-      kout[r] = k;
-      vout[r] = v;
+      r = cnt[w][d];
+      if (below == 0) cnt[w][d] = r + uint32_t(__popcll(same));
     }
-    __syncthreads();
-    base[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
-    __syncthreads();
+    rank[j] = r + below;
+  }
+  __syncthreads();
+
+  // thread d: the first position of digit d in the tile's sorted order and of each
+  // wavefront's keys of d; where the tile's run of d starts in the output
+  const int d = t;
+  const uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d];
+  const uint32_t own = c0 + c1 + c2 + cnt[3][d];
+  uint32_t total;
+  const uint32_t lstart = block_excl_scan_u32(own, wsum, &total);
+  const uint32_t dstart = block_excl_scan_u32(totals[d], wsum, &total);
+  cnt[0][d] = lstart;
+  cnt[1][d] = lstart + c0;
+  cnt[2][d] = lstart + c0 + c1;
+  cnt[3][d] = lstart + c0 + c1 + c2;
+  gbase[d] = dstart + counts[size_t(d) * ntiles + tile] - lstart;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSortKPT; ++j) {
+    if (w * Q + j * 64 + lane < tn) {
+      const uint32_t pos = cnt[w][uint32_t(k[j] >> shift) & 0xffu] + rank[j];
+      if (pos < uint32_t(kSortTile)) {  // always true; keeps a logic error inside the tile
+        sk[pos] = k[j];
+        sv[pos] = v[j];
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < tn; i += kSortThreads) {
+    const uint64_t kk = sk[i];
+    const uint32_t pos = gbase[uint32_t(kk >> shift) & 0xffu] + uint32_t(i);
+    if (int64_t(pos) < n) {  // always true; keeps a logic error inside the output
+      kout[pos] = kk;
+      vout[pos] = sv[i];
+    }
   }
 }
 
@@ -582,16 +644,16 @@ __global__ __launch_bounds__(kMexTile, LB <= 10 ? 3 : 2) void mex_force_kernel(c
 namespace {
 
 struct MexLayout {
-  size_t off_key0, off_key1, off_idx0, off_idx1, off_hist, off_tot, off_tsum, off_toff, off_bsum,
+  size_t off_key0, off_key1, off_idx0, off_idx1, off_sort, sort_bytes, off_tsum, off_toff, off_bsum,
       total;
-  int nblk, ntiles, nblocks, lb;
+  int stiles, ntiles, nblocks, lb;
 };
 
 MexLayout mex_layout(int64_t n, int lmax) {
   MexLayout L{};
   L.lb = lmax <= 2 ? 2 : lmax <= 6 ? 6 : lmax <= 10 ? 10 : 14;
-  L.nblk = int((n + kSortSeg - 1) / kSortSeg);
-  if (L.nblk < 1) L.nblk = 1;
+  L.stiles = int((n + kSortTile - 1) / kSortTile);
+  if (L.stiles < 1) L.stiles = 1;
   L.ntiles = int((n + kMexTile - 1) / kMexTile);
   if (L.ntiles < 1) L.ntiles = 1;
   L.nblocks = (L.ntiles + kMexBlockTiles - 1) / kMexBlockTiles;
@@ -607,8 +669,9 @@ MexLayout mex_layout(int64_t n, int lmax) {
   L.off_key1 = take(nn * 8);
   L.off_idx0 = take(nn * 4);
   L.off_idx1 = take(nn * 4);
-  L.off_hist = take(size_t(256) * L.nblk * 4);
-  L.off_tot = take(size_t(256) * 4);
+  // radix sort: digit counts [256][tiles], digit totals [256]
+  L.sort_bytes = size_t(256) * L.stiles * 4 + size_t(256) * 4;
+  L.off_sort = take(L.sort_bytes);
   L.off_tsum = take(size_t(L.ntiles) * 2 * NC * 8);
   L.off_toff = take(size_t(L.ntiles) * 2 * NC * 8);
   L.off_bsum = take(size_t(L.nblocks) * 2 * NC * 8);
@@ -685,8 +748,8 @@ int launch_mex_force(const double* x, const double* y, const double* z, const do
   uint64_t* k1 = reinterpret_cast<uint64_t*>(base + L.off_key1);
   uint32_t* i0 = reinterpret_cast<uint32_t*>(base + L.off_idx0);
   uint32_t* i1 = reinterpret_cast<uint32_t*>(base + L.off_idx1);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(base + L.off_hist);
-  uint32_t* tot = reinterpret_cast<uint32_t*>(base + L.off_tot);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(base + L.off_sort);
+  uint32_t* totals = counts + size_t(256) * L.stiles;
   double* tsum = reinterpret_cast<double*>(base + L.off_tsum);
   double* toff = reinterpret_cast<double*>(base + L.off_toff);
   double* bsum = reinterpret_cast<double*>(base + L.off_bsum);
@@ -694,13 +757,13 @@ int launch_mex_force(const double* x, const double* y, const double* z, const do
   hipLaunchKernelGGL(mex_keys_kernel, dim3(int((n + 255) / 256)), dim3(256), 0, st, x, y, z, n, k0, i0);
   int rc = hip_fail(hipGetLastError(), "mex_keys_kernel launch");
   if (rc) return rc;
-  for (int pass = 0; pass < 8; ++pass) {
+  for (int pass = 0; pass < kSortPasses; ++pass) {
     const int shift = 8 * pass;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(L.nblk), dim3(kSortThreads), 0, st, k0, n, shift,
-                       L.nblk, hist);
-    hipLaunchKernelGGL(radix_digit_scan_kernel, dim3(256), dim3(256), 0, st, hist, L.nblk, tot);
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(L.nblk), dim3(kSortThreads), 0, st, k0, i0, k1, i1,
-                       n, shift, L.nblk, hist, tot);
+    hipLaunchKernelGGL(radix_count_kernel, dim3(L.stiles), dim3(kSortThreads), 0, st, k0, n, shift, L.stiles,
+                       counts);
+    hipLaunchKernelGGL(radix_digit_scan_kernel, dim3(256), dim3(256), 0, st, counts, L.stiles, totals);
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(L.stiles), dim3(kSortThreads), 0, st, k0, i0, k1, i1, n,
+                       shift, L.stiles, counts, totals);
     rc = hip_fail(hipGetLastError(), "radix sort launch");
     if (rc) return rc;
     uint64_t* tk = k0;
