@@ -775,29 +775,56 @@ __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coe
   w.init(lds_raw, a.tp, a.lmax, a.nmax, a.nblocks, a.streams, a.nchunks);
   const int tpr = DUAL ? a.tp / 2 : a.tp;  // particles per tile
   const int nunits = a.ustart[a.nsys];
-  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+  // particles [ub, ue) of unit u
+  auto range = [&](int u, int64_t& ub, int64_t& ue) {
     const int s = a.usys[u];
     int64_t b = a.offsets[s], e = a.offsets[s + 1];
     b = b < 0 ? 0 : (b > a.ntotal ? a.ntotal : b);
     e = e < b ? b : (e > a.ntotal ? a.ntotal : e);
-    const int64_t ub = b + int64_t(u - a.ustart[s]) * a.unit;
-    const int64_t ue = ub + a.unit < e ? ub + a.unit : e;
+    ub = b + int64_t(u - a.ustart[s]) * a.unit;
+    ue = ub + a.unit < e ? ub + a.unit : e;
+  };
+  // particle data of this lane for a tile; each tile's data is loaded while the previous
+  // tile's outer products run (the first tile of the workgroup's next unit during the
+  // last tile of the current one)
+  double xd = 0.0, yd = 0.0, zd = 0.0, md = 0.0, vxd = 0.0, vyd = 0.0, vzd = 0.0;
+  auto load_particle = [&](int64_t ub, int64_t ue, int tile) {
+    const int64_t pi = ub + int64_t(tile) * tpr + w.pidx;
+    const bool valid = w.pidx < tpr && pi < ue;
+    xd = valid ? a.x[pi] : 0.0;
+    yd = valid ? a.y[pi] : 0.0;
+    zd = valid ? a.z[pi] : 0.0;
+    md = valid ? a.m[pi] : 0.0;
+    if constexpr (DUAL) {
+      vxd = valid ? a.vx[pi] : 0.0;
+      vyd = valid ? a.vy[pi] : 0.0;
+      vzd = valid ? a.vz[pi] : 0.0;
+    }
+  };
+  int64_t ub = 0, ue = 0;
+  if (int(blockIdx.x) < nunits) {
+    range(blockIdx.x, ub, ue);
+    load_particle(ub, ue, 0);
+  }
+  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
     const int ntiles = int((ue - ub + tpr - 1) / tpr);
+    const int un = u + gridDim.x;  // this workgroup's next unit
+    int64_t nb = 0, ne = 0;
+    if (un < nunits) range(un, nb, ne);
     w.zero_slots();
     w.clear_wide();
     __syncthreads();
     int tcount = 0;
     for (int tile = 0; tile < ntiles; ++tile) {
-      const int64_t pi = ub + int64_t(tile) * tpr + w.pidx;
-      const bool valid = w.pidx < tpr && pi < ue;
       if constexpr (DUAL)
-        w.phase1_dual(valid ? a.x[pi] : 0.0, valid ? a.y[pi] : 0.0, valid ? a.z[pi] : 0.0,
-                      valid ? a.vx[pi] : 0.0, valid ? a.vy[pi] : 0.0, valid ? a.vz[pi] : 0.0,
-                      valid ? a.m[pi] : 0.0);
+        w.phase1_dual(xd, yd, zd, vxd, vyd, vzd, md);
       else
-        w.phase1(valid ? a.x[pi] : 0.0, valid ? a.y[pi] : 0.0, valid ? a.z[pi] : 0.0,
-                 valid ? a.m[pi] : 0.0);
+        w.phase1(xd, yd, zd, md);
       __syncthreads();
+      if (tile + 1 < ntiles)
+        load_particle(ub, ue, tile + 1);
+      else if (un < nunits)
+        load_particle(nb, ne, 0);
       w.phase2();
       if (++tcount == a.flush_tiles) {
         tcount = 0;
@@ -805,9 +832,12 @@ __global__ __launch_bounds__(kCoeffThreads, sizeof(T) == 4 ? 2 : 1) void scf_coe
       }
       __syncthreads();
     }
+    if (ntiles == 0 && un < nunits) load_particle(nb, ne, 0);
     w.fold();
     w.merge_write(lds_raw, reinterpret_cast<typename W::PT*>(a.partials) + size_t(u) * 2 * a.K, a.K);
     __syncthreads();
+    ub = nb;
+    ue = ne;
   }
 }
 
