@@ -4,7 +4,10 @@
 One step = one full SCF force calculation of the workload through the C-ABI:
 etics_scf_coeffs (coefficients summed over all particles) followed by
 etics_scf_force (potential and acceleration of every particle), inputs and outputs
-resident in HBM.  The headline workload is N = 10^6 particles of a triaxial
+resident in HBM.  The timed steps issue the two calls eagerly with nothing else in
+the timed region; the same steps are then run again with events around the calls and
+their main kernels (stage and kernel durations), and replayed from a captured hipGraph
+(stages_ms.graph_ms_per_step).  The headline workload is N = 10^6 particles of a triaxial
 Hernquist model (x,y,z scaled 1 : 0.8 : 0.6, seed 2) at (nmax, lmax) = (10, 10) in
 the mixed mode (FP32 basis and synthesis, FP64 coefficient reduction); the plain
 FP64 path is timed beside it.  Accuracy of both is measured against the FP64 CPU
@@ -200,36 +203,41 @@ def main():
 
         for _ in range(warmup):
             step()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        # the headline: eager calls, nothing else in the timed region
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        eager_wall = time.perf_counter() - t0
+        # the same calls with events around them and around their main kernels
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        torch.cuda.synchronize()
         for k in range(steps):
             step(evs[k])
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
         res = {
-            "wall_s": wall,
+            "wall_s": eager_wall,
             "coeff_call_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
             "force_call_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in evs])),
             "step_ms_sd": float(np.std([e[0].elapsed_time(e[2]) for e in evs])),
             "coeff_kernel_ms": kc.mean_ms(),
             "force_kernel_ms": kf.mean_ms(),
         }
-        # the same step captured once into a graph and replayed (the calls allocate and
-        # synchronise nothing, so they can be captured)
+        # the same step captured once into a graph (the calls allocate and synchronise
+        # nothing, so they can be captured) and replayed
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             etics.etics_scf_coeffs(x, y, z, m, nmax, lmax, prec, A, B, ws)
             etics.etics_scf_force(x, y, z, nmax, lmax, A, B, prec, etics.ETICS_POT_ACC, pot, ax, ay, az, ws)
-        g.replay()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(warmup):
+            g.replay()
         torch.cuda.synchronize()
-        e0.record(stream)
+        t0 = time.perf_counter()
         for _ in range(steps):
             g.replay()
-        e1.record(stream)
         torch.cuda.synchronize()
-        res["graph_ms_per_step"] = e0.elapsed_time(e1) / steps
+        res["graph_ms_per_step"] = (time.perf_counter() - t0) / steps * 1e3
         out = [t.cpu().numpy() for t in (A, B, pot, ax, ay, az)]
         return res, out
 
@@ -251,7 +259,8 @@ def main():
     lb_force = 2 if lmax <= 2 else (lmax + 1) // 2 * 2
     lb_coeff = 2 if lmax <= 2 else (6 if lmax <= 6 else (10 if lmax <= 10 else 14))
     nb = 9 if nmax + 1 <= 9 else (11 if nmax + 1 <= 11 else 12)
-    coeff_name = f"scf_coeff_kernel<float, {lb_coeff}, {nb}, 4, 0, {plan['nw']}, 0>"
+    coeff_name = (f"scf_coeff_kernel<float, {lb_coeff}, {nb}, 4, 0, {plan['nw']}, 0, false, "
+                  f"{'true' if plan['phase2'] == 2 else 'false'}>")
     kernels = {
         "force": (mixed["force_kernel_ms"], ff, f"scf_force_kernel<float, {lb_force}, true, 0>"),
         "coeff": (mixed["coeff_kernel_ms"], fc, coeff_name),
@@ -286,6 +295,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "nmax": nmax, "lmax": lmax, "seed": 2,
                    "axes": [1.0, 0.8, 0.6], "precision": "mixed: fp32 basis/synthesis, fp64 reduction",
+                   "execution": "etics_scf_coeffs + etics_scf_force issued eagerly per step "
+                                "(graph replay: stages_ms.graph_ms_per_step)",
                    "coeff_plan": plan},
         "stages_ms": {k: v for k, v in mixed.items() if k != "wall_s"},
         "step_tflops": step_tflops,
