@@ -82,6 +82,28 @@ def test_mex_ties_keep_index_order(E, orc):
     check("mex ties", got, ref, F64_MED, F64_P99, F64_MAX)
 
 
+def test_mex_equal_keys_across_sort_tiles(E, orc):
+    """Large groups of bitwise-equal keys spread over many sort tiles (2048 keys each):
+    the 8 sign flips of 1500 points, each flip a block of 1500 consecutive indices, and
+    3000 particles at one point in the middle.  Equal keys must come out in index order
+    across tiles and within a tile's digit runs (a particle out of order changes a force
+    by a pair term, ~1e-4 relative here).  The coincident cluster's forces are small
+    sums of large terms, so the plain oracle's sequential sweep is itself off by up to
+    ~1e-11 there; the comparison is with the long-double oracle."""
+    p = W.make_config(4, 1500)
+    base = np.stack([p.x, p.y, p.z], 1)
+    flips = [np.array([sx, sy, sz]) for sx in (1, -1) for sy in (1, -1) for sz in (1, -1)]
+    same = np.tile(base[7], (3000, 1))
+    pts = np.concatenate([base * f for f in flips[:4]] + [same] + [base * f for f in flips[4:]])
+    m = np.full(pts.shape[0], 1.0 / pts.shape[0])
+    x, y, z = (np.ascontiguousarray(pts[:, k]) for k in range(3))
+    got = gpu_mex(E, x, y, z, m, 6, FP64)
+    ref = orc.mex_force(x, y, z, m, 6)
+    ref_ld = orc.mex_force(x, y, z, m, 6, ext=True)
+    print("plain oracle vs long double:", acc.summarize(acc.force_rel_err(*ref[1:], *ref_ld[1:])), flush=True)
+    check("mex equal keys across tiles", got, ref_ld, F64_MED, F64_P99, F64_MAX)
+
+
 def test_mex_near_ties_below_key_precision(E, orc):
     """A cluster whose radii differ by ~2^-40 relative (below FP32 resolution) placed
     in reverse index order.  The force on a particle changes by a whole pair term
