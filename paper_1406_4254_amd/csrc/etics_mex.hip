@@ -23,10 +23,13 @@
 //   4. tile offsets: exclusive prefix (inward) and suffix (outward) over tiles, in
 //      three parallel steps (sums of blocks of tiles, a scan over the blocks, then the
 //      tiles of every block).
-//   5. mex_force: per tile, the summands again, exclusive scans inside the tile (each
-//      column staged in LDS, scanned by one wavefront with DPP lane moves), plus the tile
-//      offsets, give q and p of every particle; then the synthesis and the Cartesian
-//      force, scattered back to the caller's order.
+//   5. mex_force: per tile (one wavefront, two particles per lane), the summands again;
+//      exclusive scans inside the tile, in registers with DPP lane moves (prefix over
+//      the lanes for inward sums, the same tree over the reversed lanes for outward
+//      sums), plus the tile offsets, give q and p of every particle; then the synthesis
+//      and the Cartesian force, scattered back to the caller's order.  The FP64 mode
+//      stages each column in LDS instead (one particle per thread), scanned by one
+//      wavefront with the same lane tree.
 // Radial powers, moments, scans and synthesis accumulations are FP64 in every mode;
 // the MIXED modes evaluate Ybar_lm, its derivatives and (cos, sin)(m phi) in FP32.
 #include <hip/hip_runtime.h>
@@ -39,7 +42,7 @@
 
 namespace etics {
 
-constexpr int kMexTile = 128;       // sorted particles per tile (one per thread, 2 wavefronts)
+constexpr int kMexTile = 128;  // sorted particles per tile (tile sums: one per thread; force: two per lane)
 // LDS column of a tile in the tile-sum kernel: the rows in 16 groups of 8 (one group per
 // lane of a 16-lane DPP row), with 2 doubles of padding after every second group, so
 // the four 16-byte reads of a group by 8 neighbouring lanes fall on distinct banks
@@ -346,15 +349,6 @@ __device__ __forceinline__ double row16_incl_prefix(double x) {
 __device__ __forceinline__ double wave_excl_prefix(double x) {
   return dpp_move<kDppWaveShr1, 0xf>(wave_incl_prefix(x));
 }
-// sum over the wavefront, the same in every lane
-__device__ __forceinline__ double wave_sum(double x) {
-  const long long b = __double_as_longlong(wave_incl_prefix(x));
-  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), 63);
-  const int hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) |
-                              static_cast<long long>(static_cast<unsigned int>(lo)));
-}
-
 // The 8 rows of group g of a padded column (rows 8g .. 8g+7), four 16-byte reads
 __device__ __forceinline__ void mex_group_read(const double* col, int g, double (&v)[8]) {
   const double2* p = reinterpret_cast<const double2*>(col + mex_row_pos(8 * g));
@@ -521,9 +515,175 @@ __global__ __launch_bounds__(256) void mex_tile_offsets_kernel(const MexArgs<LB>
   }
 }
 
-// per-particle synthesis
+// the value of lane 63 - lane (one wavefront): the lane order reversed
+__device__ __forceinline__ double lane_reverse(double x) {
+  const int addr = (63 - int(threadIdx.x & 63)) << 2;
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, int(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned int>(lo)));
+}
+// exclusive suffix over lanes lane+1..63 (0 in lane 63): the prefix tree run on the
+// reversed lane order
+__device__ __forceinline__ double wave_excl_suffix(double x) {
+  return lane_reverse(wave_excl_prefix(lane_reverse(x)));
+}
+
+// Moments of one column at the two particles of a lane (sorted rows 2k and 2k+1 of the
+// tile): inward = exclusive prefix along the tile's order, outward = exclusive suffix;
+// `off` is the tile's offset from the other tiles.  The pair sum is scanned over the
+// lanes, then the pair's first row in scan order takes the scan value and the second
+// adds the first's summand.
+__device__ __forceinline__ void mex_pair_inward(double s0, double s1, double off, double& v0, double& v1) {
+  const double base = off + wave_excl_prefix(s0 + s1);
+  v0 = base;
+  v1 = base + s0;
+}
+__device__ __forceinline__ void mex_pair_outward(double s0, double s1, double off, double& v0, double& v1) {
+  const double base = off + wave_excl_suffix(s1 + s0);
+  v1 = base;
+  v0 = base + s1;
+}
+
+// Angular sums of one l at one particle, over m, from the moments: with
+// A = v^c cos m phi + v^s sin m phi and B = v^s cos m phi - v^c sin m phi (v = q inward,
+// p outward) and w = (2 - delta_m0) 4 pi / (2l + 1):
+//   y = sum w Ybar A,  d = sum w dYbar/dtheta A,  s = sum w (m Ybar / sin theta) B.
+// Then Phi -= y_q r^-(l+1) + y_p r^l, a_r += d/dr of the same, a_theta and a_phi take d
+// and s with the (1/r) x radial factors.
+struct MexLSums {
+  double yq = 0.0, yp = 0.0, dq = 0.0, dp = 0.0, sq = 0.0, sp = 0.0;
+};
+template <typename T, int LB, int l, int m>
+__device__ __forceinline__ void mex_lsums_add(const MexLane<T, LB>& q, double qc, double qs, double pc,
+                                              double ps, MexLSums& S) {
+  const T w = T((m == 0 ? 1.0 : 2.0) * 4.0 * kPi / (2.0 * l + 1.0));
+  const double c = double(q.cm[m]), s = double(q.sm[m]);
+  const double Aq = m > 0 ? qc * c + qs * s : qc;  // cm[0] = 1, sm[0] = 0
+  const double Ap = m > 0 ? pc * c + ps * s : pc;
+  const double wy = double(w * q.Y[l][m]);
+  S.yq += wy * Aq;
+  S.yp += wy * Ap;
+  if constexpr (l >= 1) {
+    T dY;
+    if constexpr (m == 0) {
+      dY = T(kTab.e1[l][0]) * q.Y[l][1];
+    } else if constexpr (m + 1 <= l) {
+      dY = T(kTab.e1[l][m]) * q.Y[l][m + 1] - T(kTab.e2[l][m]) * q.Y[l][m - 1];
+    } else {
+      dY = -T(kTab.e2[l][m]) * q.Y[l][m - 1];
+    }
+    const double wd = double(w * dY);
+    S.dq += wd * Aq;
+    S.dp += wd * Ap;
+    if constexpr (m >= 1) {
+      const T mYs = -(T(kTab.f1[l][m]) * q.Y[l + 1][m + 1] + T(kTab.f2[l][m]) * q.Y[l + 1][m - 1]);
+      const double wm = double(w * mYs);
+      S.sq += wm * (qs * c - qc * s);
+      S.sp += wm * (ps * c - pc * s);
+    }
+  }
+}
+// radial factors of one l: inward r^-(l+1), outward r^l; d/dr; and (1/r) x factor.  At
+// the origin rinv = 0 and rm = 0, so every inward factor is 0 there (no inward part)
+// without a branch.
+template <int l>
+__device__ __forceinline__ void mex_lsums_apply(const MexLSums& S, double rl, double rm, double rlm1,
+                                                double rinv, double& Phi, double& ar, double& at, double& ap) {
+  Phi -= S.yq * rm + S.yp * rl;
+  ar += S.yq * (-(l + 1.0) * rm * rinv) + S.yp * (double(l) * rlm1);
+  if constexpr (l >= 1) {
+    const double oq = rm * rinv, op = rlm1;
+    at += S.dq * oq + S.dp * op;
+    ap += S.sq * oq + S.sp * op;
+  }
+}
+
+// Per-particle synthesis.  Every wavefront takes a tile of kMexTile sorted particles on
+// its own (lane k: rows 2k and 2k+1), so no LDS and no barrier: each column's moments
+// come from lane scans in registers (inward: the prefix tree over the lanes; outward:
+// the same tree over the reversed lanes), one l at a time.
+constexpr int kMexForceWaves = 4;  // independent wavefronts (tiles) per workgroup
 template <typename T, int LB>
-__global__ __launch_bounds__(kMexTile, LB <= 10 ? 3 : 2) void mex_force_kernel(const MexArgs<LB> a) {
+__global__ __launch_bounds__(64 * kMexForceWaves, LB <= 10 ? 2 : 1) void mex_force_kernel(
+    const MexArgs<LB> a) {
+  constexpr int NC = mex_nc(LB);
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * kMexForceWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (tile >= a.ntiles) return;  // the whole wavefront
+  MexLane<T, LB> q0, q1;
+  const int64_t k0 = int64_t(tile) * kMexTile + 2 * lane;
+  q0.load(a, k0);
+  q1.load(a, k0 + 1);
+  mex_legendre_row<T, LB, 1>(q0.Y, q0.p.ct, q0.p.st);
+  mex_legendre_row<T, LB, 1>(q1.Y, q1.p.ct, q1.p.st);
+  double rl0 = 1.0, rm0 = q0.p.rinv, rlm10 = 0.0;  // r^l, r^-(l+1), r^(l-1) (0 for l = 0)
+  double rl1 = 1.0, rm1 = q1.p.rinv, rlm11 = 0.0;
+  double Phi0 = 0.0, ar0 = 0.0, at0 = 0.0, ap0 = 0.0;
+  double Phi1 = 0.0, ar1 = 0.0, at1 = 0.0, ap1 = 0.0;
+  const double* offs = a.toff + size_t(tile) * 2 * NC;
+  static_for<LB + 1>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    if (l > a.lmax) return;
+    // one l at a time: nothing of a later l is computed early, so the live registers
+    // (and with them the occupancy) stay bounded
+    __builtin_amdgcn_sched_barrier(0);
+    mex_legendre_row<T, LB, l + 1>(q0.Y, q0.p.ct, q0.p.st);  // row l+1 (for m Ybar / sin)
+    mex_legendre_row<T, LB, l + 1>(q1.Y, q1.p.ct, q1.p.st);
+    // summand weights m r^l (inward), m r^-(l+1) (outward); 0 for an invalid row
+    const double wi0 = q0.valid ? q0.p.mass * rl0 : 0.0, wo0 = q0.valid ? q0.p.mass * rm0 : 0.0;
+    const double wi1 = q1.valid ? q1.p.mass * rl1 : 0.0, wo1 = q1.valid ? q1.p.mass * rm1 : 0.0;
+    const double* oin = offs + mex_coff(l);
+    const double* oout = offs + NC + mex_coff(l);
+    MexLSums S0, S1;
+    static_for<l + 1>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      constexpr int sc = m == 0 ? 0 : 2 * m - 1;
+      double qc0, qc1, pc0, pc1, qs0 = 0.0, qs1 = 0.0, ps0 = 0.0, ps1 = 0.0;
+      {
+        const double b0 = double(q0.Y[l][m] * q0.cm[m]), b1 = double(q1.Y[l][m] * q1.cm[m]);
+        mex_pair_inward(wi0 * b0, wi1 * b1, oin[sc], qc0, qc1);
+        mex_pair_outward(wo0 * b0, wo1 * b1, oout[sc], pc0, pc1);
+      }
+      if constexpr (m > 0) {
+        const double b0 = double(q0.Y[l][m] * q0.sm[m]), b1 = double(q1.Y[l][m] * q1.sm[m]);
+        mex_pair_inward(wi0 * b0, wi1 * b1, oin[sc + 1], qs0, qs1);
+        mex_pair_outward(wo0 * b0, wo1 * b1, oout[sc + 1], ps0, ps1);
+      }
+      mex_lsums_add<T, LB, l, m>(q0, qc0, qs0, pc0, ps0, S0);
+      mex_lsums_add<T, LB, l, m>(q1, qc1, qs1, pc1, ps1, S1);
+    });
+    mex_lsums_apply<l>(S0, rl0, rm0, rlm10, q0.p.rinv, Phi0, ar0, at0, ap0);
+    mex_lsums_apply<l>(S1, rl1, rm1, rlm11, q1.p.rinv, Phi1, ar1, at1, ap1);
+    rlm10 = rl0;
+    rl0 *= q0.p.r;
+    rm0 *= q0.p.rinv;
+    rlm11 = rl1;
+    rl1 *= q1.p.r;
+    rm1 *= q1.p.rinv;
+  });
+  auto store = [&](const MexLane<T, LB>& q, double Phi, double ar, double at, double ap) {
+    if (!q.valid) return;
+    const uint32_t pidx = q.pidx;
+    if (a.want_pot) a.pot[pidx] = Phi;
+    if (a.want_acc) {
+      const double st = double(q.p.st), ct = double(q.p.ct), cp = double(q.p.cp), sp = double(q.p.sp);
+      a.ax[pidx] = st * cp * ar + ct * cp * at - sp * ap;
+      a.ay[pidx] = st * sp * ar + ct * sp * at + cp * ap;
+      a.az[pidx] = ct * ar - st * at;
+    }
+  };
+  store(q0, Phi0, ar0, at0, ap0);
+  store(q1, Phi1, ar1, at1, ap1);
+}
+
+// Per-particle synthesis with the summands staged in LDS (the FP64 mode: its basis in
+// FP64 does not leave the registers for two particles per lane).  One thread per
+// particle, two wavefronts per tile; per l and side, every column is scanned by one
+// wavefront.
+template <typename T, int LB>
+__global__ __launch_bounds__(kMexTile, LB <= 10 ? 3 : 2) void mex_force_staged_kernel(const MexArgs<LB> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* S = reinterpret_cast<double*>(lds_raw);  // [2l+1][kMexTile], one side at a time
   constexpr int NC = mex_nc(LB);
@@ -682,10 +842,9 @@ MexLayout mex_layout(int64_t n, int lmax) {
 template <typename T, int LB>
 int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
   // largest LDS blocks: 2l+1 columns (one side) at l = LB, of kMexColStride (tile sums)
-  // or kMexTile (force) doubles; at most 29 columns of 144 doubles (33.4 KiB): within
-  // the default LDS limit
+  // or kMexTile (FP64 force) doubles; at most 29 columns of 144 doubles (33.4 KiB):
+  // within the default LDS limit.  The FP32-basis force kernel uses no LDS.
   const size_t lds_sums = size_t(kMexColStride) * (2 * LB + 1) * 8;
-  const size_t lds = size_t(kMexTile) * (2 * LB + 1) * 8;
   hipLaunchKernelGGL((mex_tile_sums_kernel<T, LB>), dim3(ntiles), dim3(kMexTile), lds_sums, st, a);
   int rc = hip_fail(hipGetLastError(), "mex_tile_sums_kernel launch");
   if (rc) return rc;
@@ -697,7 +856,13 @@ int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
   if (rc) return rc;
   rc = hook_before(st);
   if (rc) return rc;
-  hipLaunchKernelGGL((mex_force_kernel<T, LB>), dim3(ntiles), dim3(kMexTile), lds, st, a);
+  if constexpr (sizeof(T) == 8) {
+    const size_t lds = size_t(kMexTile) * (2 * LB + 1) * 8;
+    hipLaunchKernelGGL((mex_force_staged_kernel<T, LB>), dim3(ntiles), dim3(kMexTile), lds, st, a);
+  } else {
+    hipLaunchKernelGGL((mex_force_kernel<T, LB>), dim3((ntiles + kMexForceWaves - 1) / kMexForceWaves),
+                       dim3(64 * kMexForceWaves), 0, st, a);
+  }
   rc = hip_fail(hipGetLastError(), "mex_force_kernel launch");
   return rc ? rc : hook_after(st);
 }
