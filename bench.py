@@ -91,6 +91,24 @@ def measured_traffic(which, workload):
     return rec["hbm_bytes_per_launch"]
 
 
+def measured_counters(which, workload, kernel):
+    """Per-particle VALU figures (rocprofv3 SQ counters) from the committed counter
+    summary of this kernel and workload, or None if there is none, it covers another
+    kernel, or the kernel's sources changed since."""
+    prec = "mixed" if kernel.startswith(f"scf_{which}_kernel<float") else "fp64"
+    path = os.path.join(ROOT, "profiles", f"counters_{which}_kernel_{prec}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        m = re.search(r"^counters_json:\s*(\{.*\})\s*$", fh.read(), re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha256") != source_digest(which) or rec.get("kernel") != kernel:
+        return None
+    return rec
+
+
 def cpu_model():
     """CPU model name of the host (from /proc/cpuinfo), or None."""
     try:
@@ -276,6 +294,17 @@ def main():
                 "frac_of_nonpacked_fp32": achieved / (PEAK_FP32_VECTOR_TFLOPS / 2)}
     if traffic is not None:
         roofline["traffic_frac_of_hbm_peak"] = traffic / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBS
+    # executed VALU work from the committed SQ counter summary, over this run's kernel time
+    ctr = measured_counters(dom, workload, dom_name)
+    if ctr is not None:
+        ex = ctr["executed_fp32_flop_per_unit"] * n / (dom_ms * 1e-3) / 1e12
+        roofline["counters"] = {
+            "valu_instr_per_particle": ctr["valu_instr_per_unit"],
+            "valu_issue_busy": ctr["valu_issue_busy"],
+            "executed_fp32_flop_per_particle": ctr["executed_fp32_flop_per_unit"],
+            "executed_tflops": ex, "executed_frac": ex / PEAK_FP32_VECTOR_TFLOPS,
+            "source": "profiles/counters_*_kernel_mixed_" + workload + ".md (SQ_INSTS_VALU, "
+                      "SQ_ACTIVE_INST_VALU, SQ_INSTS_VALU_FLOPS_FP32, GRBM_GUI_ACTIVE)"}
     other = "coeff" if dom == "force" else "force"
     o_ms, o_fpp, o_name = kernels[other]
     step_tflops = (fc + ff) * n / (ms_per_step * 1e-3) / 1e12
