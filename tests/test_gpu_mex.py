@@ -50,15 +50,31 @@ def test_mex_fp64_matches_oracle(E, orc, lmax):
     check(f"mex fp64 l{lmax}", got, ref, F64_MED, F64_P99, F64_MAX)
 
 
-@pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 4097, 9000])
-def test_mex_ragged_sizes(E, orc, n):
+@pytest.mark.parametrize("n", [1, 2, 127, 128, 129, 255, 256, 257, 4097, 9000])
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_mex_ragged_sizes(E, orc, n, prec):
+    """Partly filled tiles (128 sorted particles each; the mixed kernel holds two per
+    lane) and single tiles."""
     p = W.make_config(4, n)
-    got = gpu_mex(E, p.x, p.y, p.z, p.m, 4, FP64)
+    got = gpu_mex(E, p.x, p.y, p.z, p.m, 4, prec)
     ref = orc.mex_force(p.x, p.y, p.z, p.m, 4)
     if n == 1:  # a lone particle feels nothing
         assert np.all(got[0] == 0.0) and np.all(got[1] == 0.0)
         return
-    check(f"mex ragged n{n}", got, ref, F64_MED, F64_P99, F64_MAX)
+    if prec == FP64:
+        check(f"mex ragged n{n}", got, ref, F64_MED, F64_P99, F64_MAX)
+    else:
+        check(f"mex ragged n{n} mixed", got, ref, 1e-5, 1e-4)
+
+
+@pytest.mark.parametrize("lmax", [0, 2, 5, 9, 12, 14])
+def test_mex_mixed_lmax_buckets(E, orc, lmax):
+    """Every compiled cutoff bucket of the mixed synthesis (lmax <= 2, 6, 10, 14), with
+    lmax below and at the bucket's top."""
+    p = W.make_config(4, 3001)
+    got = gpu_mex(E, p.x, p.y, p.z, p.m, lmax, MIXED)
+    ref = orc.mex_force(p.x, p.y, p.z, p.m, lmax)
+    check(f"mex mixed l{lmax}", got, ref, 1e-5, 1e-4)
 
 
 @pytest.mark.parametrize("prec", [MIXED, COMP32])
@@ -126,15 +142,19 @@ def test_mex_near_ties_below_key_precision(E, orc):
     check("mex near ties", got, ref, F64_MED, F64_P99, F64_MAX)
 
 
-def test_mex_origin_particle(E, orc):
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_mex_origin_particle(E, orc, prec):
     p = W.make_config(4, 700)
     x, y, z = p.x.copy(), p.y.copy(), p.z.copy()
     x[5] = y[5] = z[5] = 0.0
     x[9] = y[9] = 0.0
-    got = gpu_mex(E, x, y, z, p.m, 5, FP64)
+    got = gpu_mex(E, x, y, z, p.m, 5, prec)
     ref = orc.mex_force(x, y, z, p.m, 5)
     assert all(np.all(np.isfinite(g)) for g in got)
-    check("mex origin", got, ref, F64_MED, F64_P99, F64_MAX)
+    if prec == FP64:
+        check("mex origin", got, ref, F64_MED, F64_P99, F64_MAX)
+    else:
+        check("mex origin mixed", got, ref, 1e-5, 1e-4)
 
 
 def test_mex_output_modes(E):
