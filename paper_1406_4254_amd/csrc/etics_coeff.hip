@@ -358,15 +358,18 @@ struct BatchedReduceArgs {
   double scale[(NCAP + 1) * (LCAP + 1)];
 };
 
-// one workgroup per system: its units' partials summed in unit order
+// a system's units' partials summed in unit order: workgroup (s, j) takes entries
+// [64 j, 64 j + 64) of system s, one per lane, the loads of several units in flight
+constexpr int kReduceLanes = 64;
 template <int MODE>
-__global__ __launch_bounds__(256) void scf_reduce_batched_kernel(const BatchedReduceArgs a) {
+__global__ __launch_bounds__(kReduceLanes) void scf_reduce_batched_kernel(const BatchedReduceArgs a) {
   using PT = typename PartialT<MODE>::type;
   const int s = blockIdx.x;
   const int u0 = a.ustart[s], u1 = a.ustart[s + 1];
   const size_t stride = size_t(2) * a.K;
   const int L2 = (a.lmax + 1) * (a.lmax + 2) / 2;
-  for (int c = threadIdx.x; c < 2 * a.K; c += blockDim.x) {
+  const int c = blockIdx.y * kReduceLanes + threadIdx.x;
+  if (c < 2 * a.K) {
     const int k = c < a.K ? c : c - a.K;
     const int n = k / L2;
     const int lm = k - n * L2;
@@ -377,16 +380,18 @@ __global__ __launch_bounds__(256) void scf_reduce_batched_kernel(const BatchedRe
     double* dst = (is_sin ? a.B : a.A) + size_t(s) * a.K + k;
     if (is_sin && m == 0) {
       *dst = 0.0;
-      continue;
+      return;
     }
     const PT* p = reinterpret_cast<const PT*>(a.partials) + c;
     double v;
     if constexpr (MODE == 0) {
       double acc = 0.0;
+#pragma unroll 8
       for (int u = u0; u < u1; ++u) acc += p[size_t(u) * stride];
       v = acc;
     } else {
       float2 acc = make_float2(0.f, 0.f);
+#pragma unroll 8
       for (int u = u0; u < u1; ++u) acc = merge(acc, p[size_t(u) * stride]);
       v = double(acc.x) + double(acc.y);
     }
@@ -410,10 +415,11 @@ int launch_coeff_reduce_batched(const CoeffPlan& p, const void* partials, const 
   r.nmax = p.nmax;
   r.lmax = p.lmax;
   fill_scale(r.scale, p.nmax, p.lmax, kBasisHO);
+  const dim3 grid(nsys, (2 * r.K + kReduceLanes - 1) / kReduceLanes);
   if (p.prec == ETICS_MIXED_COMP32)
-    hipLaunchKernelGGL(scf_reduce_batched_kernel<1>, dim3(nsys), dim3(256), 0, st, r);
+    hipLaunchKernelGGL(scf_reduce_batched_kernel<1>, grid, dim3(kReduceLanes), 0, st, r);
   else
-    hipLaunchKernelGGL(scf_reduce_batched_kernel<0>, dim3(nsys), dim3(256), 0, st, r);
+    hipLaunchKernelGGL(scf_reduce_batched_kernel<0>, grid, dim3(kReduceLanes), 0, st, r);
   return hip_fail(hipGetLastError(), "scf_reduce_batched_kernel launch");
 }
 
