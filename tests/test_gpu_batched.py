@@ -61,6 +61,26 @@ def test_batched_coeffs_and_force_match_oracle(E, orc, prec):
             assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4 and ep["p99"] <= 1e-4, (s, ef, ep)
 
 
+@pytest.mark.parametrize("prec", [FP64, MIXED, COMP32])
+def test_batched_systems_of_many_units(E, orc, prec):
+    """A system of ~10 work units (4096 particles each) next to one- and two-unit ones:
+    the per-system reduction adds many unit partials (double-float pairs in COMP32)."""
+    p = W.batched_systems(nsys=4, seed=42, nlog=(3.0, 4.75))
+    sizes = np.diff(p.offsets)
+    assert sizes.max() > 8 * 4096, sizes
+    nmax, lmax = 6, 4
+    K = E.etics_coeff_count(nmax, lmax)
+    x, y, z, m, off = dev(p.x, p.y, p.z, p.m, p.offsets)
+    A, B = E.etics_scf_coeffs_batched(x, y, z, m, off, nmax, lmax, prec)
+    A, B = A.cpu().numpy(), B.cpu().numpy()
+    tol = 3e-14 if prec == FP64 else 1e-5
+    for s in range(len(sizes)):
+        b, e = p.offsets[s], p.offsets[s + 1]
+        rA, rB = orc.scf_coeffs(p.x[b:e], p.y[b:e], p.z[b:e], p.m[b:e], nmax, lmax)
+        er = acc.coeff_errors(A[s * K:(s + 1) * K], B[s * K:(s + 1) * K], rA, rB)
+        assert er["norm_rel"] < tol, (s, int(sizes[s]), er)
+
+
 def test_batched_equals_single_system_calls(E):
     p = small_batch(nsys=6, seed=32)
     nmax, lmax = 6, 4
