@@ -17,9 +17,12 @@
 //      digit counts of every tile of keys, a scan of each digit's counts over the tiles,
 //      then every tile ranks its keys stably in LDS and writes them as runs of equal
 //      digit.  Stable, so equal keys stay in index order.
-//   3. mex_tile_sums: per tile of sorted particles, the sums of the inward and outward
-//      summands (FP64); each 16-lane row of a wavefront sums one LDS column, a lane
-//      adding 8 consecutive rows before a row tree.
+//   3. tile sums: per tile of 128 sorted particles, the sums of the inward and outward
+//      summands (FP64).  FP32-basis modes (mex_tile_sums_pair_kernel): one wavefront per
+//      tile, two particles per lane; the lane pair sums go through the wavefront's own
+//      LDS block and each 16-lane DPP row sums one column (4 rows a lane, then a row
+//      tree).  FP64 (mex_tile_sums_kernel): one particle per thread, each 16-lane row
+//      sums one LDS column, a lane adding 8 consecutive rows before a row tree.
 //   4. tile offsets: exclusive prefix (inward) and suffix (outward) over tiles, in
 //      three parallel steps (sums of blocks of tiles, a scan over the blocks, then the
 //      tiles of every block).
@@ -446,6 +449,86 @@ __global__ __launch_bounds__(kMexTile) void mex_tile_sums_kernel(const MexArgs<L
   });
 }
 
+// orders a wavefront's LDS accesses (lanes read what other lanes of it wrote)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Tile sums with two particles per lane (the FP32-basis modes): every wavefront takes a
+// tile of kMexTile sorted particles on its own (lane k: rows 2k and 2k+1).  Per l and
+// side the lanes write their pair sums (one row per lane) to the wavefront's own LDS
+// block, then each 16-lane DPP row sums one column: a lane adds 4 consecutive rows,
+// then a row tree.  Half the LDS traffic of one particle per thread, and no workgroup
+// barrier.
+constexpr int kMexPairWaves = 2;                    // wavefronts (tiles) per workgroup
+constexpr int kMexPairStride = 64 + 2 * (64 / 16);  // doubles per column: 64 rows, padded
+// padded position of row r: 2 doubles after every 16 rows, so the 16-byte reads of 8
+// neighbouring lanes (4 rows each) fall on distinct banks
+__device__ __forceinline__ int mex_pair_pos(int r) { return r + 2 * (r >> 4); }
+constexpr size_t mex_pair_lds_bytes(int lb) {
+  return size_t(kMexPairWaves) * (2 * lb + 1) * kMexPairStride * 8;
+}
+static_assert(mex_pair_lds_bytes(14) <= 65536, "MEX tile-sum LDS beyond the default limit");
+
+template <typename T, int LB>
+__global__ __launch_bounds__(64 * kMexPairWaves) void mex_tile_sums_pair_kernel(const MexArgs<LB> a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  constexpr int NC = mex_nc(LB);
+  constexpr int CS = kMexPairStride;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile = blockIdx.x * kMexPairWaves + wave;
+  if (tile >= a.ntiles) return;  // the whole wavefront
+  double* S = reinterpret_cast<double*>(lds_raw) + wave * (2 * LB + 1) * CS;
+  const int drow = lane >> 4, k = lane & 15;  // DPP row (column of a group of 4), group
+  MexLane<T, LB> q0, q1;
+  const int64_t k0 = int64_t(tile) * kMexTile + 2 * lane;
+  q0.load(a, k0);
+  q1.load(a, k0 + 1);
+  double rl0 = 1.0, rm0 = q0.p.rinv, rl1 = 1.0, rm1 = q1.p.rinv;  // r^l, r^-(l+1)
+  double* out = a.tsum + size_t(tile) * 2 * NC;
+  static_for<LB + 1>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    if (l > a.lmax) return;
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (l >= 1) {
+      mex_legendre_row<T, LB, l>(q0.Y, q0.p.ct, q0.p.st);
+      mex_legendre_row<T, LB, l>(q1.Y, q1.p.ct, q1.p.st);
+    }
+    constexpr int H = 2 * l + 1;
+    static_for<2>([&](auto sidec) {
+      constexpr int side = decltype(sidec)::value;
+      const double w0 = q0.valid ? q0.p.mass * (side == 0 ? rl0 : rm0) : 0.0;
+      const double w1 = q1.valid ? q1.p.mass * (side == 0 ? rl1 : rm1) : 0.0;
+      static_for<l + 1>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        constexpr int sc = m == 0 ? 0 : 2 * m - 1;
+        S[sc * CS + mex_pair_pos(lane)] =
+            w0 * double(q0.Y[l][m] * q0.cm[m]) + w1 * double(q1.Y[l][m] * q1.cm[m]);
+        if constexpr (m > 0)
+          S[(sc + 1) * CS + mex_pair_pos(lane)] =
+              w0 * double(q0.Y[l][m] * q0.sm[m]) + w1 * double(q1.Y[l][m] * q1.sm[m]);
+      });
+      wave_lds_sync();
+      static_for<(H + 3) / 4>([&](auto jc) {
+        const int c = 4 * decltype(jc)::value + drow;
+        const int cc = c < H ? c : H - 1;  // rows past the last column read a valid one
+        const double2* g = reinterpret_cast<const double2*>(S + cc * CS + mex_pair_pos(4 * k));
+        const double2 u = g[0], v = g[1];
+        const double tot = row16_incl_prefix(((u.x + u.y) + v.x) + v.y);
+        if (k == 15 && c < H) out[side * NC + mex_coff(l) + c] = tot;
+      });
+      wave_lds_sync();  // the next side or l writes the block again
+    });
+    rl0 *= q0.p.r;
+    rm0 *= q0.p.rinv;
+    rl1 *= q1.p.r;
+    rm1 *= q1.p.rinv;
+  });
+}
+
 // tile offsets, step 1: sums of blocks of kMexBlockTiles tiles (one workgroup per block)
 template <int LB>
 __global__ __launch_bounds__(256) void mex_block_sums_kernel(const MexArgs<LB> a) {
@@ -845,7 +928,11 @@ int launch_mex_lb(const MexArgs<LB>& a, int ntiles, hipStream_t st) {
   // or kMexTile (FP64 force) doubles; at most 29 columns of 144 doubles (33.4 KiB):
   // within the default LDS limit.  The FP32-basis force kernel uses no LDS.
   const size_t lds_sums = size_t(kMexColStride) * (2 * LB + 1) * 8;
-  hipLaunchKernelGGL((mex_tile_sums_kernel<T, LB>), dim3(ntiles), dim3(kMexTile), lds_sums, st, a);
+  if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL((mex_tile_sums_pair_kernel<T, LB>), dim3((ntiles + kMexPairWaves - 1) / kMexPairWaves),
+                       dim3(64 * kMexPairWaves), mex_pair_lds_bytes(LB), st, a);
+  else
+    hipLaunchKernelGGL((mex_tile_sums_kernel<T, LB>), dim3(ntiles), dim3(kMexTile), lds_sums, st, a);
   int rc = hip_fail(hipGetLastError(), "mex_tile_sums_kernel launch");
   if (rc) return rc;
   hipLaunchKernelGGL((mex_block_sums_kernel<LB>), dim3(a.nblocks), dim3(256), 0, st, a);
