@@ -69,15 +69,11 @@ struct ForceArgs {
   LfUpdate lf;     // lf.mode = 0: write a; otherwise update v (and x) instead
 };
 
-// potential / acceleration of point i from one system's prepared coefficients cf
-template <typename T, int LB, bool ACC, int BASIS = kBasisHO>
-__device__ __forceinline__ void force_point(const ForceArgs& a, const T* __restrict__ cf,
-                                            int64_t i) {
-  const Sph<T> s = sph<T, BASIS>(a.x[i], a.y[i], a.z[i]);
-  const ForceOut<T> o = synth_point<T, LB, ACC, BASIS>(s, cf, a.K, a.nmax, a.lmax);
-  if (a.want_pot) a.pot[i] = double(o.pot);
+// the outputs of point i: potential and acceleration, or the leapfrog update
+template <typename T, bool ACC>
+__device__ __forceinline__ void force_store(const ForceArgs& a, int64_t i, T pot, T gx, T gy, T gz) {
+  if (a.want_pot) a.pot[i] = double(pot);
   if constexpr (ACC) {
-    const T gx = o.gx, gy = o.gy, gz = o.gz;
     if (a.lf.mode == 0) {
       a.ax[i] = double(gx);
       a.ay[i] = double(gy);
@@ -104,12 +100,43 @@ __device__ __forceinline__ void force_point(const ForceArgs& a, const T* __restr
   }
 }
 
+// potential / acceleration of point i from one system's prepared coefficients cf
+template <typename T, int LB, bool ACC, int BASIS = kBasisHO>
+__device__ __forceinline__ void force_point(const ForceArgs& a, const T* __restrict__ cf,
+                                            int64_t i) {
+  const Sph<T> s = sph<T, BASIS>(a.x[i], a.y[i], a.z[i]);
+  const ForceOut<T> o = synth_point<T, LB, ACC, BASIS>(s, cf, a.K, a.nmax, a.lmax);
+  force_store<T, ACC>(a, i, o.pot, o.gx, o.gy, o.gz);
+}
+
 template <typename T, int LB, bool ACC, int BASIS>
 __global__ __launch_bounds__(256) void scf_force_kernel(const ForceArgs a) {
   const T* __restrict__ cf = reinterpret_cast<const T*>(a.cf);
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
        i += int64_t(gridDim.x) * blockDim.x)
     force_point<T, LB, ACC, BASIS>(a, cf, i);
+}
+
+// FP64: the workgroup copies the prepared coefficients to LDS ([K][4]) once and every
+// lane reads them as broadcast VGPR operands (as SGPR operands each FP64 coefficient
+// takes two SGPRs and the n loop's set overflows them); a grid of a few workgroups per
+// CU, each walking many points, keeps the copies few.
+template <int LB, bool ACC, int BASIS>
+__global__ __launch_bounds__(256) void scf_force_lds_kernel(const ForceArgs a) {
+  extern __shared__ __align__(16) double lds_cf[];
+  const double* __restrict__ cf = reinterpret_cast<const double*>(a.cf);
+  for (int i = threadIdx.x; i < 4 * a.K; i += blockDim.x) {
+    const int which = i / a.K, idx = i - which * a.K;
+    lds_cf[4 * idx + which] = cf[i];
+  }
+  __syncthreads();
+  const LdsCoeffs<double> src{lds_cf};
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const Sph<double> s = sph<double, BASIS>(a.x[i], a.y[i], a.z[i]);
+    const ForceOut<double> o = synth_point_src<double, LB, ACC, BASIS>(s, src, a.nmax, a.lmax);
+    force_store<double, ACC>(a, i, o.pot, o.gx, o.gy, o.gz);
+  }
 }
 
 // batched systems: `split` workgroups per unit of `unit` particles of one system (each a
@@ -151,13 +178,31 @@ struct BatchInfo {
   int nsys, unit, split;
 };
 
+// the whole 160 KiB of a CU may be requested as dynamic LDS (the largest cutoffs' FP64
+// coefficients take 80 KiB); hipFuncSetAttribute once per kernel (failures surface at
+// the launch)
+void set_lds_limit(const void* kfn) {
+  hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
 template <typename T, bool ACC, int LBV>
 void launch_force_kernel(const ForceArgs& a, int basis, int grid, const BatchInfo* bi,
                          hipStream_t st) {
   if (bi)
     hipLaunchKernelGGL((scf_force_batched_kernel<T, LBV, ACC>), dim3(grid), dim3(256), 0, st, a,
                        bi->offsets, bi->ustart, bi->usys, bi->nsys, bi->unit, bi->split);
-  else if (basis == kBasisCB)
+  else if constexpr (sizeof(T) == 8) {
+    // a few workgroups per CU, each with the coefficients in LDS
+    const size_t lds = size_t(4) * a.K * sizeof(double);
+    const int g = grid < 1024 ? grid : 1024;
+    if (basis == kBasisCB) {
+      set_lds_limit(reinterpret_cast<const void*>(scf_force_lds_kernel<LBV, ACC, kBasisCB>));
+      hipLaunchKernelGGL((scf_force_lds_kernel<LBV, ACC, kBasisCB>), dim3(g), dim3(256), lds, st, a);
+    } else {
+      set_lds_limit(reinterpret_cast<const void*>(scf_force_lds_kernel<LBV, ACC, kBasisHO>));
+      hipLaunchKernelGGL((scf_force_lds_kernel<LBV, ACC, kBasisHO>), dim3(g), dim3(256), lds, st, a);
+    }
+  } else if (basis == kBasisCB)
     hipLaunchKernelGGL((scf_force_kernel<T, LBV, ACC, kBasisCB>), dim3(grid), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL((scf_force_kernel<T, LBV, ACC, kBasisHO>), dim3(grid), dim3(256), 0, st, a);
