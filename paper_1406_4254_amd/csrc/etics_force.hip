@@ -105,7 +105,7 @@ template <typename T, int LB, bool ACC, int BASIS = kBasisHO>
 __device__ __forceinline__ void force_point(const ForceArgs& a, const T* __restrict__ cf,
                                             int64_t i) {
   const Sph<T> s = sph<T, BASIS>(a.x[i], a.y[i], a.z[i]);
-  const ForceOut<T> o = synth_point<T, LB, ACC, BASIS>(s, cf, a.K, a.nmax, a.lmax);
+  const ForceOut<T> o = synth_point<T, LB, ACC, BASIS>(s, ConstPtr<T>(cf), a.K, a.nmax, a.lmax);
   force_store<T, ACC>(a, i, o.pot, o.gx, o.gy, o.gz);
 }
 
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void scf_force_kernel(const ForceArgs a) {
     force_point<T, LB, ACC, BASIS>(a, cf, i);
 }
 
-// FP64: the workgroup copies the prepared coefficients to LDS ([K][4]) once and every
+// FP64: the workgroup copies the prepared coefficients to LDS once, as [K][4], and every
 // lane reads them as broadcast VGPR operands (as SGPR operands each FP64 coefficient
 // takes two SGPRs and the n loop's set overflows them); a grid of a few workgroups per
 // CU, each walking many points, keeps the copies few.
@@ -130,11 +130,12 @@ __global__ __launch_bounds__(256) void scf_force_lds_kernel(const ForceArgs a) {
     lds_cf[4 * idx + which] = cf[i];
   }
   __syncthreads();
-  const LdsCoeffs<double> src{lds_cf};
+  const LdsPtr<double> src = (LdsPtr<double>)(lds_cf);
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
        i += int64_t(gridDim.x) * blockDim.x) {
     const Sph<double> s = sph<double, BASIS>(a.x[i], a.y[i], a.z[i]);
-    const ForceOut<double> o = synth_point_src<double, LB, ACC, BASIS>(s, src, a.nmax, a.lmax);
+    const ForceOut<double> o =
+        synth_point<double, LB, ACC, BASIS, LdsPtr<double>, true>(s, src, a.K, a.nmax, a.lmax);
     force_store<double, ACC>(a, i, o.pot, o.gx, o.gy, o.gz);
   }
 }

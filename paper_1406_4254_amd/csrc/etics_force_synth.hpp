@@ -40,37 +40,32 @@ template <typename S>
 __device__ __forceinline__ Dual<S> cload(const __attribute__((address_space(4))) Dual<S>* p) {
   return Dual<S>(p->v, p->d);
 }
-
-// Where the synthesis reads the prepared coefficients: array `which` (0..3) entry idx.
-// ScalarCoeffs: the caller's [4][K] array through the constant address space, so the
-// wave-uniform loads become scalar loads into SGPR operands.  LdsCoeffs: a workgroup's
-// copy in LDS laid out [K][4], read by every lane at the same address (a broadcast) into
-// VGPR operands; used in FP64, where each coefficient takes two SGPRs.
+// ... or from a workgroup's copy in LDS: every lane reads the same address (a broadcast)
+// into VGPR operands (FP64, where each coefficient would take two SGPRs)
 template <typename T>
-struct ScalarCoeffs {
-  const T* cf;
-  int K;
-  __device__ __forceinline__ T get(int which, int idx) const {
-    return cload((const __attribute__((address_space(4))) T*)(cf) + which * K + idx);
-  }
-};
+__device__ __forceinline__ T cload(const __attribute__((address_space(3))) T* p) {
+  return *p;
+}
 template <typename T>
-struct LdsCoeffs {
-  const T* lds;  // [K][4] in LDS
-  __device__ __forceinline__ T get(int which, int idx) const { return lds[4 * idx + which]; }
-};
+using ConstPtr = const __attribute__((address_space(4))) T*;
+template <typename T>
+using LdsPtr = const __attribute__((address_space(3))) T*;
 
 // Potential and acceleration (-grad Phi, Cartesian) at a point with spherical
-// coordinates s, from one system's prepared coefficients (src).  T is the compute type,
+// coordinates s, from one system's prepared coefficients cf.  T is the compute type,
 // or Dual<S> to carry every quantity's time derivative along the motion (the jerk).
 template <typename T>
 struct ForceOut {
   T pot, gx, gy, gz;
 };
 
-template <typename T, int LB, bool ACC, int BASIS, typename Src = ScalarCoeffs<T>>
-__device__ __forceinline__ ForceOut<T> synth_point_src(const Sph<T>& s, const Src& src, int nmax,
-                                                       int lmax) {
+// cf: the coefficients' four arrays, through the constant address space (ConstPtr) or
+// in LDS (LdsPtr); laid out [4][K], or with QUAD [K][4] (the four values of a
+// coefficient side by side, two 16-byte reads in FP64)
+template <typename T, int LB, bool ACC, int BASIS, typename P = ConstPtr<T>, bool QUAD = false>
+__device__ __forceinline__ ForceOut<T> synth_point(const Sph<T>& s, P cf, int K, int nmax, int lmax) {
+  const int WK = QUAD ? 1 : K;      // offset from one array to the next
+  constexpr int IS = QUAD ? 4 : 1;  // offset from one coefficient to the next
   using S = typename ScalarOf<T>::type;
   const BasisTables<S>& tb = tab<S>();
   const int L2 = (lmax + 1) * (lmax + 2) / 2;
@@ -124,12 +119,12 @@ __device__ __forceinline__ ForceOut<T> synth_point_src(const Sph<T>& s, const Sr
       // the prepared coefficients are read-only here: through the constant address
       // space their wave-uniform loads become scalar loads into SGPR operands (for FP64
       // as well, where the generic pointer left the compiler with per-lane loads)
-      const int il = l * (l + 1) / 2;  // index of (n = 0, l, m = 0)
+      const P cfl = cf + l * (l + 1) / 2 * IS;
       T U[l + 1], V[l + 1], W[l + 1], X[l + 1];
 #pragma unroll
       for (int m = 0; m <= l; ++m) {
-        U[m] = src.get(0, il + m);
-        V[m] = m > 0 ? src.get(1, il + m) : T(0);
+        U[m] = cload(cfl + m * IS);
+        V[m] = m > 0 ? cload(cfl + WK + m * IS) : T(0);
         W[m] = T(0);
         X[m] = T(0);
       }
@@ -141,18 +136,18 @@ __device__ __forceinline__ ForceOut<T> synth_point_src(const Sph<T>& s, const Sr
       auto step = [&](int nn, T& cA, T& cB, T& eA, T& eB) {
         // on entry cA = Chat_{nn-2}, cB = Chat_{nn-1}; on exit cA = Chat_nn
         cA = s.xi * cB - ql[nn] * cA;
-        const int in = il + nn * L2;
+        const auto* cn = cfl + nn * L2 * IS;
 #pragma unroll
         for (int m = 0; m <= l; ++m) {
-          U[m] = fma_(cA, src.get(0, in + m), U[m]);
-          if (m > 0) V[m] = fma_(cA, src.get(1, in + m), V[m]);
+          U[m] = fma_(cA, cload(cn + m * IS), U[m]);
+          if (m > 0) V[m] = fma_(cA, cload(cn + WK + m * IS), V[m]);
         }
         if constexpr (ACC) {
           // eB = Ehat_{nn-1} is used, then eA <- Ehat_nn
 #pragma unroll
           for (int m = 0; m <= l; ++m) {
-            W[m] = fma_(eB, src.get(2, in + m), W[m]);
-            if (m > 0) X[m] = fma_(eB, src.get(3, in + m), X[m]);
+            W[m] = fma_(eB, cload(cn + 2 * WK + m * IS), W[m]);
+            if (m > 0) X[m] = fma_(eB, cload(cn + 3 * WK + m * IS), X[m]);
           }
           eA = s.xi * eB - qdl[nn] * eA;
         }
@@ -229,12 +224,6 @@ __device__ __forceinline__ ForceOut<T> synth_point_src(const Sph<T>& s, const Sr
     }
   }
   return out;
-}
-
-template <typename T, int LB, bool ACC, int BASIS>
-__device__ __forceinline__ ForceOut<T> synth_point(const Sph<T>& s, const T* __restrict__ cf, int K,
-                                                   int nmax, int lmax) {
-  return synth_point_src<T, LB, ACC, BASIS>(s, ScalarCoeffs<T>{cf, K}, nmax, lmax);
 }
 
 }  // namespace etics

@@ -95,7 +95,8 @@ template <typename S, int LB>
 __device__ __forceinline__ void jerk_point(const JerkArgs& a, const Dual<S>* __restrict__ cf,
                                            int64_t i) {
   const Sph<Dual<S>> s = sph_dual<S, kBasisHO>(a.x[i], a.y[i], a.z[i], a.vx[i], a.vy[i], a.vz[i]);
-  const ForceOut<Dual<S>> o = synth_point<Dual<S>, LB, true, kBasisHO>(s, cf, a.K, a.nmax, a.lmax);
+  const ForceOut<Dual<S>> o =
+      synth_point<Dual<S>, LB, true, kBasisHO>(s, ConstPtr<Dual<S>>(cf), a.K, a.nmax, a.lmax);
   const double g[3] = {double(o.gx.v), double(o.gy.v), double(o.gz.v)};
   const double jk[3] = {double(o.gx.d), double(o.gy.d), double(o.gz.d)};
   double* A[3] = {a.ax, a.ay, a.az};
