@@ -143,13 +143,15 @@ __global__ __launch_bounds__(256) void scf_force_lds_kernel(const ForceArgs a) {
 // batched systems: `split` workgroups per unit of `unit` particles of one system (each a
 // contiguous part of it), so the coefficient pointer (and with it every coefficient
 // operand) is uniform across the workgroup; splitting the coefficient kernel's units
-// gives the force pass more workgroups
+// gives the force pass more workgroups.  FP64: the system's prepared coefficients are
+// copied to LDS as [K][4] first, as in scf_force_lds_kernel.
 template <typename T, int LB, bool ACC>
 __global__ __launch_bounds__(256) void scf_force_batched_kernel(const ForceArgs a,
                                                                 const int64_t* __restrict__ offsets,
                                                                 const int* __restrict__ ustart,
                                                                 const int* __restrict__ usys,
                                                                 int nsys, int unit, int split) {
+  extern __shared__ __align__(16) double lds_cf[];
   const int u = blockIdx.x / split;
   const int part = blockIdx.x % split;
   if (u >= ustart[nsys]) return;
@@ -163,7 +165,22 @@ __global__ __launch_bounds__(256) void scf_force_batched_kernel(const ForceArgs 
   const int64_t ub = u0 + part * kPart < ue0 ? u0 + part * kPart : ue0;
   const int64_t ue = ub + kPart < ue0 ? ub + kPart : ue0;
   const T* __restrict__ cf = reinterpret_cast<const T*>(a.cf) + size_t(sys) * 4 * a.K;
-  for (int64_t i = ub + threadIdx.x; i < ue; i += blockDim.x) force_point<T, LB, ACC>(a, cf, i);
+  if constexpr (sizeof(T) == 8) {
+    for (int i = threadIdx.x; i < 4 * a.K; i += blockDim.x) {
+      const int which = i / a.K, idx = i - which * a.K;
+      lds_cf[4 * idx + which] = cf[i];
+    }
+    __syncthreads();
+    const LdsPtr<double> src = (LdsPtr<double>)(lds_cf);
+    for (int64_t i = ub + threadIdx.x; i < ue; i += blockDim.x) {
+      const Sph<double> s = sph<double, kBasisHO>(a.x[i], a.y[i], a.z[i]);
+      const ForceOut<double> o =
+          synth_point<double, LB, ACC, kBasisHO, LdsPtr<double>, true>(s, src, a.K, a.nmax, a.lmax);
+      force_store<double, ACC>(a, i, o.pot, o.gx, o.gy, o.gz);
+    }
+  } else {
+    for (int64_t i = ub + threadIdx.x; i < ue; i += blockDim.x) force_point<T, LB, ACC>(a, cf, i);
+  }
 }
 
 size_t force_prep_bytes(int nmax, int lmax, int prec) {
@@ -189,10 +206,12 @@ void set_lds_limit(const void* kfn) {
 template <typename T, bool ACC, int LBV>
 void launch_force_kernel(const ForceArgs& a, int basis, int grid, const BatchInfo* bi,
                          hipStream_t st) {
-  if (bi)
-    hipLaunchKernelGGL((scf_force_batched_kernel<T, LBV, ACC>), dim3(grid), dim3(256), 0, st, a,
+  if (bi) {
+    const size_t lds = sizeof(T) == 8 ? size_t(4) * a.K * sizeof(double) : 0;
+    if (lds) set_lds_limit(reinterpret_cast<const void*>(scf_force_batched_kernel<T, LBV, ACC>));
+    hipLaunchKernelGGL((scf_force_batched_kernel<T, LBV, ACC>), dim3(grid), dim3(256), lds, st, a,
                        bi->offsets, bi->ustart, bi->usys, bi->nsys, bi->unit, bi->split);
-  else if constexpr (sizeof(T) == 8) {
+  } else if constexpr (sizeof(T) == 8) {
     // a few workgroups per CU, each with the coefficients in LDS
     const size_t lds = size_t(4) * a.K * sizeof(double);
     const int g = grid < 1024 ? grid : 1024;
