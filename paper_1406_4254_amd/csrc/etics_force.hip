@@ -200,7 +200,7 @@ struct BatchInfo {
 // coefficients take 80 KiB); hipFuncSetAttribute once per kernel (failures surface at
 // the launch)
 void set_lds_limit(const void* kfn) {
-  hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 template <typename T, bool ACC, int LBV>

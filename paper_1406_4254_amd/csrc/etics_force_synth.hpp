@@ -41,10 +41,14 @@ __device__ __forceinline__ Dual<S> cload(const __attribute__((address_space(4)))
   return Dual<S>(p->v, p->d);
 }
 // ... or from a workgroup's copy in LDS: every lane reads the same address (a broadcast)
-// into VGPR operands (FP64, where each coefficient would take two SGPRs)
+// into VGPR operands (FP64 and Dual, where each coefficient would take two SGPRs)
 template <typename T>
 __device__ __forceinline__ T cload(const __attribute__((address_space(3))) T* p) {
   return *p;
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> cload(const __attribute__((address_space(3))) Dual<S>* p) {
+  return Dual<S>(p->v, p->d);
 }
 template <typename T>
 using ConstPtr = const __attribute__((address_space(4))) T*;

@@ -91,12 +91,13 @@ struct JerkArgs {
   double dt;
 };
 
-template <typename S, int LB>
-__device__ __forceinline__ void jerk_point(const JerkArgs& a, const Dual<S>* __restrict__ cf,
-                                           int64_t i) {
+// cf: the prepared coefficients through the constant address space ([4][K]) or in LDS
+// (LdsPtr, QUAD: [K][4])
+template <typename S, int LB, typename CP = ConstPtr<Dual<S>>, bool QUAD = false>
+__device__ __forceinline__ void jerk_point(const JerkArgs& a, CP cf, int64_t i) {
   const Sph<Dual<S>> s = sph_dual<S, kBasisHO>(a.x[i], a.y[i], a.z[i], a.vx[i], a.vy[i], a.vz[i]);
   const ForceOut<Dual<S>> o =
-      synth_point<Dual<S>, LB, true, kBasisHO>(s, ConstPtr<Dual<S>>(cf), a.K, a.nmax, a.lmax);
+      synth_point<Dual<S>, LB, true, kBasisHO, CP, QUAD>(s, cf, a.K, a.nmax, a.lmax);
   const double g[3] = {double(o.gx.v), double(o.gy.v), double(o.gz.v)};
   const double jk[3] = {double(o.gx.d), double(o.gy.d), double(o.gz.d)};
   double* A[3] = {a.ax, a.ay, a.az};
@@ -137,17 +138,20 @@ __global__ __launch_bounds__(256) void scf_jerk_kernel(const JerkArgs a) {
   const Dual<S>* __restrict__ cf = reinterpret_cast<const Dual<S>*>(a.cf);
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
        i += int64_t(gridDim.x) * blockDim.x)
-    jerk_point<S, LB>(a, cf, i);
+    jerk_point<S, LB>(a, ConstPtr<Dual<S>>(cf), i);
 }
 
 // batched systems: `split` workgroups per unit of `unit` particles of one system, as the
-// batched force kernel
+// batched force kernel; the workgroup first copies its system's prepared coefficients to
+// LDS as [K][4] and reads them as broadcast VGPR operands (a Dual coefficient would take
+// two SGPRs)
 template <typename S, int LB>
 __global__ __launch_bounds__(256) void scf_jerk_batched_kernel(const JerkArgs a,
                                                                const int64_t* __restrict__ offsets,
                                                                const int* __restrict__ ustart,
                                                                const int* __restrict__ usys, int nsys,
                                                                int unit, int split) {
+  extern __shared__ __align__(16) unsigned char jerk_lds[];
   const int u = blockIdx.x / split;
   const int part = blockIdx.x % split;
   if (u >= ustart[nsys]) return;
@@ -161,7 +165,15 @@ __global__ __launch_bounds__(256) void scf_jerk_batched_kernel(const JerkArgs a,
   const int64_t ub = u0 + part * kPart < ue0 ? u0 + part * kPart : ue0;
   const int64_t ue = ub + kPart < ue0 ? ub + kPart : ue0;
   const Dual<S>* __restrict__ cf = reinterpret_cast<const Dual<S>*>(a.cf) + size_t(sys) * 4 * a.K;
-  for (int64_t i = ub + threadIdx.x; i < ue; i += blockDim.x) jerk_point<S, LB>(a, cf, i);
+  Dual<S>* lds_cf = reinterpret_cast<Dual<S>*>(jerk_lds);
+  for (int i = threadIdx.x; i < 4 * a.K; i += blockDim.x) {
+    const int which = i / a.K, idx = i - which * a.K;
+    lds_cf[4 * idx + which] = cf[i];
+  }
+  __syncthreads();
+  const LdsPtr<Dual<S>> src = (LdsPtr<Dual<S>>)(lds_cf);
+  for (int64_t i = ub + threadIdx.x; i < ue; i += blockDim.x)
+    jerk_point<S, LB, LdsPtr<Dual<S>>, true>(a, src, i);
 }
 
 namespace {
@@ -175,10 +187,15 @@ struct JerkBatch {
 
 template <typename S, int LBV>
 void launch_jerk_kernel(const JerkArgs& a, int grid, const JerkBatch* bi, hipStream_t st) {
-  if (bi)
-    hipLaunchKernelGGL((scf_jerk_batched_kernel<S, LBV>), dim3(grid), dim3(256), 0, st, a, bi->offsets,
+  if (bi) {
+    // 4 K Dual values of LDS (at the largest cutoffs 79 KiB in FP32, 158 KiB in FP64;
+    // failures surface at the launch)
+    const size_t lds = size_t(4) * a.K * sizeof(Dual<S>);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(scf_jerk_batched_kernel<S, LBV>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipLaunchKernelGGL((scf_jerk_batched_kernel<S, LBV>), dim3(grid), dim3(256), lds, st, a, bi->offsets,
                        bi->ustart, bi->usys, bi->nsys, bi->unit, bi->split);
-  else
+  } else
     hipLaunchKernelGGL((scf_jerk_kernel<S, LBV>), dim3(grid), dim3(256), 0, st, a);
 }
 
