@@ -143,8 +143,9 @@ __global__ __launch_bounds__(256) void scf_force_lds_kernel(const ForceArgs a) {
 // batched systems: `split` workgroups per unit of `unit` particles of one system (each a
 // contiguous part of it), so the coefficient pointer (and with it every coefficient
 // operand) is uniform across the workgroup; splitting the coefficient kernel's units
-// gives the force pass more workgroups.  FP64: the system's prepared coefficients are
-// copied to LDS as [K][4] first, as in scf_force_lds_kernel.
+// gives the force pass more workgroups.  The system's prepared coefficients are copied
+// to LDS as [K][4] first, as in scf_force_lds_kernel, and read as broadcast VGPR
+// operands (measured faster than SGPR operands here in FP32 too).
 template <typename T, int LB, bool ACC>
 __global__ __launch_bounds__(256) void scf_force_batched_kernel(const ForceArgs a,
                                                                 const int64_t* __restrict__ offsets,
@@ -165,21 +166,17 @@ __global__ __launch_bounds__(256) void scf_force_batched_kernel(const ForceArgs 
   const int64_t ub = u0 + part * kPart < ue0 ? u0 + part * kPart : ue0;
   const int64_t ue = ub + kPart < ue0 ? ub + kPart : ue0;
   const T* __restrict__ cf = reinterpret_cast<const T*>(a.cf) + size_t(sys) * 4 * a.K;
-  if constexpr (sizeof(T) == 8) {
-    for (int i = threadIdx.x; i < 4 * a.K; i += blockDim.x) {
-      const int which = i / a.K, idx = i - which * a.K;
-      lds_cf[4 * idx + which] = cf[i];
-    }
-    __syncthreads();
-    const LdsPtr<double> src = (LdsPtr<double>)(lds_cf);
-    for (int64_t i = ub + threadIdx.x; i < ue; i += blockDim.x) {
-      const Sph<double> s = sph<double, kBasisHO>(a.x[i], a.y[i], a.z[i]);
-      const ForceOut<double> o =
-          synth_point<double, LB, ACC, kBasisHO, LdsPtr<double>, true>(s, src, a.K, a.nmax, a.lmax);
-      force_store<double, ACC>(a, i, o.pot, o.gx, o.gy, o.gz);
-    }
-  } else {
-    for (int64_t i = ub + threadIdx.x; i < ue; i += blockDim.x) force_point<T, LB, ACC>(a, cf, i);
+  T* lds_t = reinterpret_cast<T*>(lds_cf);
+  for (int i = threadIdx.x; i < 4 * a.K; i += blockDim.x) {
+    const int which = i / a.K, idx = i - which * a.K;
+    lds_t[4 * idx + which] = cf[i];
+  }
+  __syncthreads();
+  const LdsPtr<T> src = (LdsPtr<T>)(lds_t);
+  for (int64_t i = ub + threadIdx.x; i < ue; i += blockDim.x) {
+    const Sph<T> s = sph<T, kBasisHO>(a.x[i], a.y[i], a.z[i]);
+    const ForceOut<T> o = synth_point<T, LB, ACC, kBasisHO, LdsPtr<T>, true>(s, src, a.K, a.nmax, a.lmax);
+    force_store<T, ACC>(a, i, o.pot, o.gx, o.gy, o.gz);
   }
 }
 
@@ -207,7 +204,7 @@ template <typename T, bool ACC, int LBV>
 void launch_force_kernel(const ForceArgs& a, int basis, int grid, const BatchInfo* bi,
                          hipStream_t st) {
   if (bi) {
-    const size_t lds = sizeof(T) == 8 ? size_t(4) * a.K * sizeof(double) : 0;
+    const size_t lds = size_t(4) * a.K * sizeof(T);
     if (lds) set_lds_limit(reinterpret_cast<const void*>(scf_force_batched_kernel<T, LBV, ACC>));
     hipLaunchKernelGGL((scf_force_batched_kernel<T, LBV, ACC>), dim3(grid), dim3(256), lds, st, a,
                        bi->offsets, bi->ustart, bi->usys, bi->nsys, bi->unit, bi->split);
