@@ -201,4 +201,6 @@ def test_mex_cfg4_full_size(E, orc):
         if prec == FP64:
             check("mex cfg4 fp64 vs long-double oracle", got, ref_ld, 2e-14, 1.1e-13, 1.5e-13)
         else:
-            check("mex cfg4 mixed", got, ref, 1e-5, 1e-4)
+            # max: about 10x the largest error measured on MI355X (force 1.6e-6,
+            # potential 1.6e-7)
+            check("mex cfg4 mixed", got, ref, 1e-5, 1e-4, 2e-5)

@@ -164,6 +164,9 @@ def test_cfg2_full_size(E, orc):
             assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4 and ce["norm_rel"] < 1e-5
             for e in (ep, ep1):
                 assert e["median"] <= 1e-5 and e["p99"] <= 1e-4
+            # beyond the gate: every particle of the workload, about 10x the largest
+            # error measured on MI355X (force max 9.4e-7, potential max 7.2e-7)
+            assert ef["max"] < 1e-5 and ep["max"] < 1e-5 and ep1["max"] < 1e-5
 
 
 # ------------------------------------------------------------------ edge cases
