@@ -184,7 +184,10 @@ def test_cfg5_full_size_sampled(E, orc):
         rp, rx, ry, rz = orc.scf_force(p.x[b:e], p.y[b:e], p.z[b:e], nmax, lmax, rA, rB)
         ef = acc.summarize(acc.force_rel_err(ax[b:e].cpu().numpy(), ay[b:e].cpu().numpy(),
                                              az[b:e].cpu().numpy(), rx, ry, rz))
-        assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4, (s, ef)
+        print(f"cfg5 system {s} ({e - b} particles) mixed force {ef}", flush=True)
+        # max: about 10x the largest measured on MI355X over these systems (9.5e-6,
+        # at particles next to a sphere's centre, where the force tends to zero)
+        assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4 and ef["max"] < 1e-4, (s, ef)
 
 
 def test_leapfrog_step_counts_and_cache_replacement(E, orc):
