@@ -90,6 +90,9 @@ def test_cb_mixed_force_accuracy(E, orc, prec, n, nmax, lmax):
     assert ef["median"] <= 1e-5 and ef["p99"] <= 1e-4
     for e in (ep, ep1):
         assert e["median"] <= 1e-5 and e["p99"] <= 1e-4
+    # max: about 10x the largest measured on MI355X over these cases (force 4.1e-6,
+    # potential 7.7e-7)
+    assert ef["max"] < 5e-5 and ep["max"] < 5e-5 and ep1["max"] < 5e-5
 
 
 def test_cb_origin_axis_and_ragged(E, orc):

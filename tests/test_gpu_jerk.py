@@ -125,6 +125,8 @@ def test_jerk_mixed_accuracy(E, J, prec):
     ej = report(f"jerk prec{prec} jerk", vec_err(j, j_ref.numpy()))
     assert ea["median"] <= 1e-5 and ea["p99"] <= 1e-4
     assert ej["median"] <= 1e-5 and ej["p99"] <= 1e-4
+    # max: about 10x the largest measured on MI355X (acceleration 6.7e-7, jerk 1.45e-5)
+    assert ea["max"] < 1e-5 and ej["max"] < 1.5e-4
 
 
 def test_jerk_off_axis_and_origin_finite(E):
